@@ -1,0 +1,2 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench."""
+from .ncp_jacobian import CONFIGS, NCPSystem, make_config, make_poisson, make_system, random_vector  # noqa: F401
