@@ -1,0 +1,810 @@
+// Setup-phase kernels of the MGR hierarchy and the classical AMG below it.
+//
+// Every floating-point result here is produced by the same sequence of IEEE
+// operations (one rounding per product, sum or quotient; no contraction) that
+// the method's definition fixes, so the hierarchy is bit-for-bit reproducible:
+// sums run in ascending column/index order, SpGEMM accumulates each output
+// entry over ascending k, and the PMIS rounds are synchronous with integer
+// keys.
+#include <climits>
+
+#include "mgr_impl.h"
+
+namespace mgr {
+namespace {
+
+__device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+__device__ inline double row_diag(const int32_t *rp, const int32_t *ci, const double *v, int64_t i) {
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) return v[p];
+    return 0.0;
+}
+
+// ---------------- validation ----------------
+// err[0] |= 1 on a bad row; err[1] = max label; err[2] |= 1 on a label outside [0, 31]
+__global__ void k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const int32_t *lab,
+                           int *err) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    int a = rp[i], b = rp[i + 1];
+    bool bad = a < 0 || b < a || (int64_t)b > nnz;
+    if (!bad) {
+        for (int p = a; p < b; ++p) {
+            int c = ci[p];
+            if (c < 0 || (int64_t)c >= n || (p > a && c <= ci[p - 1])) {
+                bad = true;
+                break;
+            }
+        }
+    }
+    if (bad) atomicOr(&err[0], 1);
+    if (lab) {
+        int L = lab[i];
+        if (L < 0 || L > 31) atomicOr(&err[2], 1);
+        else atomicMax(&err[1], L);
+    }
+}
+
+// ---------------- cell-sliced ELL of the level-0 operator ----------------
+__global__ void k_rowlen(int64_t n, const int32_t *rp, int32_t *len) {
+    int64_t i = gtid();
+    if (i < n) len[i] = rp[i + 1] - rp[i];
+}
+
+// width of (slice s, component v) = longest row of that component in the slice
+__global__ void k_csell_width(int64_t nslice, int bs, int64_t ncell, const int32_t *rowlen, int32_t *width) {
+    int64_t g = gtid();
+    if (g >= nslice * bs) return;
+    int64_t s = g / bs;
+    int v = (int)(g % bs);
+    int w = 0;
+    for (int l = 0; l < kWave; ++l) {
+        int64_t c = s * kWave + l;
+        if (c >= ncell) break;
+        int x = rowlen[c * bs + v];
+        w = x > w ? x : w;
+    }
+    width[g] = w;
+}
+
+__global__ void k_csell_fill(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v,
+                             const int32_t *off, const int32_t *width, int32_t *col, double *val) {
+    int64_t i = gtid();
+    if (i >= ncell * bs) return;
+    int64_t c = i / bs;
+    int comp = (int)(i % bs);
+    int64_t s = c / kWave;
+    int lane = (int)(c % kWave);
+    int64_t o = off[s * bs + comp];
+    int w = width[s * bs + comp];
+    int a = rp[i], len = rp[i + 1] - a;
+    for (int t = 0; t < len && t < w; ++t) {
+        int64_t idx = (o + t) * kWave + lane;
+        col[idx] = ci[a + t];
+        val[idx] = v[a + t];
+    }
+}
+
+// ---------------- global relaxation: cell-block inverses ----------------
+// planes: binv[(r*3+q)*ncell + c] = (B_c^{-1})_{rq}; det by cofactor expansion
+// along row 0 and inv_ij = cof_ji * (1/det).  err[3] = smallest singular cell.
+__global__ void k_block_inverse(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v,
+                                double *binv, int *err) {
+    int64_t c = gtid();
+    if (c >= ncell) return;
+    double a[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    int64_t lo = (int64_t)bs * c, hi = lo + bs;
+    for (int r = 0; r < bs; ++r) {
+        int64_t i = lo + r;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            int64_t j = ci[p];
+            if (j >= lo && j < hi) a[r][j - lo] = v[p];
+        }
+    }
+    if (bs == 1) {
+        if (a[0][0] == 0.0) {
+            atomicMin(&err[3], (int)c);
+            binv[c] = 0.0;
+        } else {
+            binv[c] = 1.0 / a[0][0];
+        }
+        return;
+    }
+    double c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1];
+    double c01 = -(a[1][0] * a[2][2] - a[1][2] * a[2][0]);
+    double c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+    double c10 = -(a[0][1] * a[2][2] - a[0][2] * a[2][1]);
+    double c11 = a[0][0] * a[2][2] - a[0][2] * a[2][0];
+    double c12 = -(a[0][0] * a[2][1] - a[0][1] * a[2][0]);
+    double c20 = a[0][1] * a[1][2] - a[0][2] * a[1][1];
+    double c21 = -(a[0][0] * a[1][2] - a[0][2] * a[1][0]);
+    double c22 = a[0][0] * a[1][1] - a[0][1] * a[1][0];
+    double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
+    if (det == 0.0 || !isfinite(det)) atomicMin(&err[3], (int)c);
+    double id = 1.0 / det;
+    binv[0 * ncell + c] = c00 * id;
+    binv[1 * ncell + c] = c10 * id;
+    binv[2 * ncell + c] = c20 * id;
+    binv[3 * ncell + c] = c01 * id;
+    binv[4 * ncell + c] = c11 * id;
+    binv[5 * ncell + c] = c21 * id;
+    binv[6 * ncell + c] = c02 * id;
+    binv[7 * ncell + c] = c12 * id;
+    binv[8 * ncell + c] = c22 * id;
+}
+
+// ---------------- MGR level construction ----------------
+__global__ void k_level_flags(int64_t n, const int32_t *lab, int l, int32_t *isF, int32_t *isC) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    isF[i] = lab[i] == l;
+    isC[i] = lab[i] > l;
+}
+
+__global__ void k_level_maps(int64_t n, const int32_t *lab, int l, const int32_t *fpos, const int32_t *cpos,
+                             int32_t *fmap, int32_t *cmap, int32_t *flist, int32_t *clist) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    if (lab[i] == l) {
+        fmap[i] = fpos[i];
+        cmap[i] = -1;
+        flist[fpos[i]] = (int32_t)i;
+    } else {
+        fmap[i] = -1;
+        cmap[i] = cpos[i];
+        clist[cpos[i]] = (int32_t)i;
+    }
+}
+
+// dinv_f = 1 / a_ii (i = flist[f]); err[3] = smallest level-local row with a zero diagonal.
+// offdiag |= 1 if some F row couples to another F point (A_FF not diagonal).
+__global__ void k_fdiag_inverse(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci,
+                                const double *v, double *dinv, int *err, int *offdiag, const int32_t *fmap) {
+    int64_t f = gtid();
+    if (f >= nF) return;
+    int64_t i = flist[f];
+    double d = 0.0;
+    bool off = false;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int64_t j = ci[p];
+        if (j == i) d = v[p];
+        else if (fmap[j] >= 0) off = true;
+    }
+    if (off) atomicOr(offdiag, 1);
+    if (d == 0.0) {
+        atomicMin(&err[3], (int)i);
+        dinv[f] = 0.0;
+    } else {
+        dinv[f] = 1.0 / d;
+    }
+}
+
+// P = [W_p; I_C]: rows of the level, columns = C points
+__global__ void k_p_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cmap, int rp_type,
+                          int32_t *cnt) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    int c = 0;
+    if (cmap[i] >= 0) c = 1;
+    else if (rp_type != 2)
+        for (int p = rp[i]; p < rp[i + 1]; ++p) c += cmap[ci[p]] >= 0;
+    cnt[i] = c;
+}
+
+__global__ void k_p_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *cmap,
+                         const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Prp, int32_t *Pci,
+                         double *Pv) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    int q = Prp[i];
+    if (cmap[i] >= 0) {
+        Pci[q] = cmap[i];
+        Pv[q] = 1.0;
+        return;
+    }
+    if (rp_type == 2) return;
+    double di = dinv[fmap[i]];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        if (cmap[j] < 0) continue;
+        Pci[q] = cmap[j];
+        Pv[q] = -(v[p] * di);
+        q++;
+    }
+}
+
+// R = [W_r, I_C]: rows = C points, columns = level-local indices
+__global__ void k_r_count(int64_t nC, const int32_t *clist, const int32_t *rp, const int32_t *ci,
+                          const int32_t *fmap, int rp_type, int32_t *cnt) {
+    int64_t c = gtid();
+    if (c >= nC) return;
+    int64_t u = clist[c];
+    int k = 1;
+    if (rp_type != 1)
+        for (int p = rp[u]; p < rp[u + 1]; ++p) k += fmap[ci[p]] >= 0;
+    cnt[c] = k;
+}
+
+__global__ void k_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, const int32_t *ci, const double *v,
+                         const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Rrp, int32_t *Rci,
+                         double *Rv) {
+    int64_t c = gtid();
+    if (c >= nC) return;
+    int u = clist[c];
+    int q = Rrp[c];
+    bool placed = false;
+    if (rp_type != 1) {
+        for (int p = rp[u]; p < rp[u + 1]; ++p) {
+            int j = ci[p];
+            if (!placed && j > u) {
+                Rci[q] = u;
+                Rv[q] = 1.0;
+                q++;
+                placed = true;
+            }
+            int f = fmap[j];
+            if (f < 0) continue;
+            Rci[q] = j;
+            Rv[q] = -(v[p] * dinv[f]);
+            q++;
+        }
+    }
+    if (!placed) {
+        Rci[q] = u;
+        Rv[q] = 1.0;
+    }
+}
+
+__global__ void k_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst) {
+    int64_t i = gtid();
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+// ---------------- SpGEMM: one wavefront per output row ----------------
+// Lane l holds the entries t = l, l+64, ... of row i of A (ascending k) and a
+// cursor into row k of B.  Each step takes the smallest head column j over the
+// wavefront; the contributions to C_ij are summed in ascending t (= ascending
+// k) by walking the ballot mask, starting from 0.0.  Patterns are symbolic.
+constexpr int kSpgChunks = 8;
+
+__device__ inline int wave_min_i32(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        int o = __shfl_xor(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__restrict__ Arp,
+                                                const int32_t *__restrict__ Aci, const double *__restrict__ Av,
+                                                const int32_t *__restrict__ Brp, const int32_t *__restrict__ Bci,
+                                                const double *__restrict__ Bv, int32_t *cnt_or_Crp,
+                                                int32_t *__restrict__ Cci, double *__restrict__ Cv, int *err) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (row >= m) return;  // uniform per wavefront
+    const int a0 = Arp[row];
+    const int len = Arp[row + 1] - a0;
+    if (len > kWave * kSpgChunks) {
+        if (lane == 0) atomicOr(err, 1);
+        return;
+    }
+    const int nch = (len + kWave - 1) / kWave;
+    int p[kSpgChunks], e[kSpgChunks], hd[kSpgChunks];
+    double av[kSpgChunks];
+#pragma unroll
+    for (int c = 0; c < kSpgChunks; ++c) {
+        p[c] = 0;
+        e[c] = 0;
+        hd[c] = INT_MAX;
+        av[c] = 0.0;
+        int t = c * kWave + lane;
+        if (c < nch && t < len) {
+            int k = Aci[a0 + t];
+            if (FILL) av[c] = Av[a0 + t];
+            p[c] = Brp[k];
+            e[c] = Brp[k + 1];
+            hd[c] = p[c] < e[c] ? Bci[p[c]] : INT_MAX;
+        }
+    }
+    int out = FILL ? cnt_or_Crp[row] : 0;
+    int count = 0;
+    for (;;) {
+        int mn = INT_MAX;
+#pragma unroll
+        for (int c = 0; c < kSpgChunks; ++c)
+            if (c < nch) mn = hd[c] < mn ? hd[c] : mn;
+        mn = wave_min_i32(mn);
+        if (mn == INT_MAX) break;
+        if (FILL) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < kSpgChunks; ++c) {
+                if (c < nch) {
+                    bool hit = hd[c] == mn;
+                    double prod = hit ? av[c] * Bv[p[c]] : 0.0;
+                    unsigned long long mask = __ballot(hit);
+                    while (mask) {
+                        int l = __builtin_ctzll(mask);
+                        acc = acc + __shfl(prod, l);
+                        mask &= mask - 1;
+                    }
+                }
+            }
+            if (lane == 0) {
+                Cci[out + count] = mn;
+                Cv[out + count] = acc;
+            }
+        }
+        count++;
+#pragma unroll
+        for (int c = 0; c < kSpgChunks; ++c) {
+            if (c < nch && hd[c] == mn) {
+                p[c]++;
+                hd[c] = p[c] < e[c] ? Bci[p[c]] : INT_MAX;
+            }
+        }
+    }
+    if (!FILL && lane == 0) cnt_or_Crp[row] = count;
+}
+
+// ---------------- stable transpose ----------------
+__global__ void k_transpose_count(int64_t nrows, const int32_t *rp, const int32_t *ci, int32_t *cnt) {
+    int64_t i = gtid();
+    if (i >= nrows) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) atomicAdd(&cnt[ci[p]], 1);
+}
+
+__global__ void k_transpose_fill(int64_t nrows, const int32_t *rp, const int32_t *ci, const double *v, int32_t *next,
+                                 int32_t *Tci, double *Tv) {
+    int64_t i = gtid();
+    if (i >= nrows) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int slot = atomicAdd(&next[ci[p]], 1);
+        Tci[slot] = (int32_t)i;
+        if (Tv) Tv[slot] = v[p];
+    }
+}
+
+// the slots of a row were taken in arbitrary order; source rows are unique,
+// so sorting by source row gives the one stable order
+__global__ void k_transpose_sort(int64_t ncols, const int32_t *Trp, int32_t *Tci, double *Tv) {
+    int64_t j = gtid();
+    if (j >= ncols) return;
+    int a = Trp[j], b = Trp[j + 1];
+    for (int p = a + 1; p < b; ++p) {
+        int key = Tci[p];
+        double val = Tv ? Tv[p] : 0.0;
+        int q = p - 1;
+        while (q >= a && Tci[q] > key) {
+            Tci[q + 1] = Tci[q];
+            if (Tv) Tv[q + 1] = Tv[q];
+            q--;
+        }
+        Tci[q + 1] = key;
+        if (Tv) Tv[q + 1] = val;
+    }
+}
+
+// ---------------- classical strength of connection ----------------
+// j in S_i iff j != i, m_i > 0 and -s_i a_ij >= theta m_i, s_i = sign of a_ii (+ for 0)
+template <bool FILL>
+__global__ void k_strength(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
+                           int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    int a = rp[i], b = rp[i + 1];
+    double d = 0.0;
+    for (int p = a; p < b; ++p)
+        if (ci[p] == i) d = v[p];
+    bool pos = d >= 0.0;
+    double m = -INFINITY;
+    for (int p = a; p < b; ++p) {
+        if (ci[p] == i) continue;
+        double t = pos ? -v[p] : v[p];
+        if (t > m) m = t;
+    }
+    double thr = theta * m;
+    int q = FILL ? cnt_or_Srp[i] : 0;
+    int cnt = 0;
+    for (int p = a; p < b; ++p) {
+        bool strong = false;
+        if (ci[p] != i && m > 0.0) {
+            double t = pos ? -v[p] : v[p];
+            strong = t >= thr;
+        }
+        if (strong) {
+            if (FILL) Sci[q + cnt] = ci[p];
+            cnt++;
+        }
+        if (FILL) sflag[p] = strong ? 1 : 0;
+    }
+    if (!FILL) cnt_or_Srp[i] = cnt;
+}
+
+// ---------------- PMIS ----------------
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_pmis_init(int64_t n, const int32_t *STrp, int32_t *state) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    state[i] = (STrp[i + 1] - STrp[i]) == 0 ? -1 : 0;
+}
+
+__device__ inline bool key_gt(int li, uint64_t hi, int64_t i, int lj, uint64_t hj, int64_t j) {
+    if (li != lj) return li > lj;
+    if (hi != hj) return hi > hj;
+    return i > j;
+}
+
+// newc[i] = 1 iff i is undecided and its key (lambda, hash, index) exceeds the
+// key of every undecided point in S_i and S_i^T (state of the round's start)
+__global__ void k_pmis_select(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *STrp,
+                              const int32_t *STci, const int32_t *state, uint64_t seed, int32_t *newc) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    if (state[i] != 0) {
+        newc[i] = 0;
+        return;
+    }
+    int li = STrp[i + 1] - STrp[i];
+    uint64_t hi = splitmix64(seed ^ (uint64_t)i);
+    bool ok = true;
+    for (int p = Srp[i]; p < Srp[i + 1] && ok; ++p) {
+        int64_t j = Sci[p];
+        if (state[j] == 0 && !key_gt(li, hi, i, STrp[j + 1] - STrp[j], splitmix64(seed ^ (uint64_t)j), j)) ok = false;
+    }
+    for (int p = STrp[i]; p < STrp[i + 1] && ok; ++p) {
+        int64_t j = STci[p];
+        if (state[j] == 0 && !key_gt(li, hi, i, STrp[j + 1] - STrp[j], splitmix64(seed ^ (uint64_t)j), j)) ok = false;
+    }
+    newc[i] = ok ? 1 : 0;
+}
+
+// new C points become C; undecided points that strongly depend on a new C point become F.
+// counters[0] += undecided left, counters[1] += new C points.
+__global__ void k_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *newc,
+                              int32_t *state, int *counters) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    if (newc[i]) {
+        state[i] = 1;
+        atomicAdd(&counters[1], 1);
+        return;
+    }
+    if (state[i] != 0) return;
+    for (int p = Srp[i]; p < Srp[i + 1]; ++p)
+        if (newc[Sci[p]]) {
+            state[i] = -1;
+            return;
+        }
+    atomicAdd(&counters[0], 1);
+}
+
+__global__ void k_cf_flags(int64_t n, const int32_t *state, int32_t *isC) {
+    int64_t i = gtid();
+    if (i < n) isC[i] = state[i] == 1;
+}
+
+// ---------------- classical interpolation ----------------
+__global__ void k_interp_count(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *sflag,
+                               const int32_t *cf, int32_t *cnt) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    if (cf[i] == 1) {
+        cnt[i] = 1;
+        return;
+    }
+    int c = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) c += (sflag[p] && cf[ci[p]] == 1);
+    cnt[i] = c;
+}
+
+__device__ inline int find_col(const int32_t *cols, int len, int key) {
+    int lo = 0, hi = len - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int x = cols[mid];
+        if (x == key) return mid;
+        if (x < key) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+// For F-point i (C_i strong C neighbours, F_i strong F neighbours, W_i the rest):
+// atil = a_ii + sum_W a_in; for k in F_i ascending: den = sum_{m in C_i} abar_km
+// (abar_km = a_km when a_km a_kk < 0, else 0); den == 0 lumps a_ik into atil,
+// otherwise num_j += (a_ik abar_kj) / den; w_ij = -((a_ij + num_j) / atil).
+__global__ void k_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+                              const uint8_t *sflag, const int32_t *cf, const int32_t *cmap, const int32_t *Prp,
+                              int32_t *Pci, double *Pv) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    int base = Prp[i], nci = Prp[i + 1] - base;
+    if (cf[i] == 1) {
+        Pci[base] = cmap[i];
+        Pv[base] = 1.0;
+        return;
+    }
+    if (nci == 0) return;
+    int a = rp[i], b = rp[i + 1];
+    int t = 0;
+    for (int p = a; p < b; ++p) {
+        int j = ci[p];
+        if (sflag[p] && cf[j] == 1) {
+            Pci[base + t] = cmap[j];
+            Pv[base + t] = 0.0;
+            t++;
+        }
+    }
+    double atil = 0.0;
+    for (int p = a; p < b; ++p)
+        if (ci[p] == i) atil = v[p];
+    for (int p = a; p < b; ++p) {
+        if (ci[p] == i) continue;
+        if (!sflag[p]) atil = atil + v[p];
+    }
+    for (int p = a; p < b; ++p) {
+        int k = ci[p];
+        if (k == i || !sflag[p] || cf[k] != -1) continue;
+        double aik = v[p];
+        double akk = row_diag(rp, ci, v, k);
+        double den = 0.0;
+        for (int q = rp[k]; q < rp[k + 1]; ++q) {
+            int mcol = ci[q];
+            if (cf[mcol] != 1 || find_col(Pci + base, nci, cmap[mcol]) < 0) continue;
+            double akm = v[q];
+            double abar = (akm * akk < 0.0) ? akm : 0.0;
+            den = den + abar;
+        }
+        if (den == 0.0) {
+            atil = atil + aik;
+        } else {
+            for (int q = rp[k]; q < rp[k + 1]; ++q) {
+                int mcol = ci[q];
+                if (cf[mcol] != 1) continue;
+                int pos = find_col(Pci + base, nci, cmap[mcol]);
+                if (pos < 0) continue;
+                double akm = v[q];
+                double abar = (akm * akk < 0.0) ? akm : 0.0;
+                double prod = aik * abar;
+                Pv[base + pos] = Pv[base + pos] + prod / den;
+            }
+        }
+    }
+    t = 0;
+    for (int p = a; p < b; ++p) {
+        int j = ci[p];
+        if (!(sflag[p] && cf[j] == 1)) continue;
+        double s = v[p] + Pv[base + t];
+        Pv[base + t] = (atil == 0.0) ? 0.0 : -(s / atil);
+        t++;
+    }
+}
+
+// l1 row norms (ascending column order); err[3] = smallest empty row
+__global__ void k_l1(int64_t n, const int32_t *rp, const double *v, double *l1, int *err) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    double s = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) s = s + fabs(v[p]);
+    if (s == 0.0) atomicMin(&err[3], (int)i);
+    l1[i] = s;
+}
+
+// ---------------- coarsest level: dense LU with partial pivoting ----------------
+// One workgroup.  Pivot = first row of largest |a_ik| (ties -> lowest row).
+constexpr int kLuBT = 256;
+__global__ void __launch_bounds__(kLuBT) k_dense_lu(int64_t n, const int32_t *rp, const int32_t *ci,
+                                                    const double *v, double *lu, int32_t *perm, int *err) {
+    __shared__ double sv[kLuBT];
+    __shared__ int si[kLuBT];
+    __shared__ int piv_s, fail_s;
+    const int tid = threadIdx.x;
+    for (int64_t idx = tid; idx < n * n; idx += kLuBT) lu[idx] = 0.0;
+    __syncthreads();
+    for (int64_t i = tid; i < n; i += kLuBT) {
+        perm[i] = (int32_t)i;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) lu[i * n + ci[p]] = v[p];
+    }
+    __syncthreads();
+    for (int64_t k = 0; k < n; ++k) {
+        double best = -1.0;
+        int bi = (int)n;
+        for (int64_t i = k + tid; i < n; i += kLuBT) {
+            double a = fabs(lu[i * n + k]);
+            if (a > best) {
+                best = a;
+                bi = (int)i;
+            }
+        }
+        sv[tid] = best;
+        si[tid] = bi;
+        __syncthreads();
+        for (int off = kLuBT / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                double ob = sv[tid + off];
+                int oi = si[tid + off];
+                if (ob > sv[tid] || (ob == sv[tid] && oi < si[tid])) {
+                    sv[tid] = ob;
+                    si[tid] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            piv_s = si[0];
+            fail_s = !(sv[0] > 0.0);
+        }
+        __syncthreads();
+        if (fail_s) {
+            if (tid == 0) atomicOr(&err[4], 1);
+            return;
+        }
+        const int64_t piv = piv_s;
+        if (piv != k) {
+            for (int64_t j = tid; j < n; j += kLuBT) {
+                double x = lu[k * n + j];
+                lu[k * n + j] = lu[piv * n + j];
+                lu[piv * n + j] = x;
+            }
+            if (tid == 0) {
+                int32_t x = perm[k];
+                perm[k] = perm[piv];
+                perm[piv] = x;
+            }
+        }
+        __syncthreads();
+        const double pv = lu[k * n + k];
+        for (int64_t i = k + 1 + tid; i < n; i += kLuBT) lu[i * n + k] = lu[i * n + k] / pv;
+        __syncthreads();
+        const int64_t w = n - k - 1;
+        for (int64_t idx = tid; idx < w * w; idx += kLuBT) {
+            int64_t i = k + 1 + idx / w, j = k + 1 + idx % w;
+            lu[i * n + j] = lu[i * n + j] - lu[i * n + k] * lu[k * n + j];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_pattern_outer(int64_t n, const int32_t *rp, const int32_t *ci, const double *lam, const double *x,
+                                double *d) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    double li = lam[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) d[p] = -(li * x[ci[p]]);
+}
+
+}  // namespace
+
+constexpr int BT = 256;
+
+void launch_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const int32_t *lab, int *err,
+                     hipStream_t s) {
+    if (n > 0) k_validate<<<nblocks(n, BT), BT, 0, s>>>(n, nnz, rp, ci, lab, err);
+}
+void launch_csell_count(int64_t ncell, int bs, const int32_t *rp, int32_t *rowlen, hipStream_t s) {
+    int64_t n = ncell * bs;
+    if (n > 0) k_rowlen<<<nblocks(n, BT), BT, 0, s>>>(n, rp, rowlen);
+}
+void launch_csell_width(int64_t nslice, int bs, int64_t ncell, const int32_t *rowlen, int32_t *width,
+                        hipStream_t s) {
+    if (nslice > 0) k_csell_width<<<nblocks(nslice * bs, BT), BT, 0, s>>>(nslice, bs, ncell, rowlen, width);
+}
+void launch_csell_fill(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v,
+                       const int32_t *off, const int32_t *width, int32_t *col, double *val, hipStream_t s) {
+    if (ncell > 0) k_csell_fill<<<nblocks(ncell * bs, BT), BT, 0, s>>>(ncell, bs, rp, ci, v, off, width, col, val);
+}
+void launch_block_inverse(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v, double *binv,
+                          int *err, hipStream_t s) {
+    if (ncell > 0) k_block_inverse<<<nblocks(ncell, BT), BT, 0, s>>>(ncell, bs, rp, ci, v, binv, err);
+}
+void launch_level_flags(int64_t n, const int32_t *lab, int l, int32_t *isF, int32_t *isC, hipStream_t s) {
+    if (n > 0) k_level_flags<<<nblocks(n, BT), BT, 0, s>>>(n, lab, l, isF, isC);
+}
+void launch_level_maps(int64_t n, const int32_t *lab, int l, const int32_t *fpos, const int32_t *cpos, int32_t *fmap,
+                       int32_t *cmap, int32_t *flist, int32_t *clist, hipStream_t s) {
+    if (n > 0) k_level_maps<<<nblocks(n, BT), BT, 0, s>>>(n, lab, l, fpos, cpos, fmap, cmap, flist, clist);
+}
+void launch_fdiag_inverse(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
+                          double *dinv, int *err, int *offdiag_flag, const int32_t *fmap, hipStream_t s) {
+    if (nF > 0)
+        k_fdiag_inverse<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, v, dinv, err, offdiag_flag, fmap);
+}
+void launch_p_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cmap, int rp_type, int32_t *cnt,
+                    hipStream_t s) {
+    if (n > 0) k_p_count<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, cmap, rp_type, cnt);
+}
+void launch_p_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *cmap,
+                   const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Prp, int32_t *Pci, double *Pv,
+                   hipStream_t s) {
+    if (n > 0) k_p_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, cmap, fmap, dinv, rp_type, Prp, Pci, Pv);
+}
+void launch_r_count(int64_t nC, const int32_t *clist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
+                    int rp_type, int32_t *cnt, hipStream_t s) {
+    if (nC > 0) k_r_count<<<nblocks(nC, BT), BT, 0, s>>>(nC, clist, rp, ci, fmap, rp_type, cnt);
+}
+void launch_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, const int32_t *ci, const double *v,
+                   const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Rrp, int32_t *Rci,
+                   double *Rv, hipStream_t s) {
+    if (nC > 0)
+        k_r_fill<<<nblocks(nC, BT), BT, 0, s>>>(nC, clist, rp, ci, v, fmap, dinv, rp_type, Rrp, Rci, Rv);
+}
+void launch_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst, hipStream_t s) {
+    if (n > 0) k_gather_i32<<<nblocks(n, BT), BT, 0, s>>>(n, idx, src, dst);
+}
+int spgemm_max_row() { return kWave * kSpgChunks; }
+void launch_spgemm(int pass, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,
+                   const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci, double *Cv, int *err,
+                   hipStream_t s) {
+    if (m <= 0) return;
+    const int rows_per_block = BT / kWave;
+    unsigned g = nblocks(m, rows_per_block);
+    if (pass == 0)
+        k_spgemm<false><<<g, BT, 0, s>>>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err);
+    else
+        k_spgemm<true><<<g, BT, 0, s>>>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err);
+}
+void launch_transpose_count(int64_t nrows, const int32_t *rp, const int32_t *ci, int32_t *cnt, hipStream_t s) {
+    if (nrows > 0) k_transpose_count<<<nblocks(nrows, BT), BT, 0, s>>>(nrows, rp, ci, cnt);
+}
+void launch_transpose_fill(int64_t nrows, const int32_t *rp, const int32_t *ci, const double *v, int32_t *next,
+                           int32_t *Tci, double *Tv, hipStream_t s) {
+    if (nrows > 0) k_transpose_fill<<<nblocks(nrows, BT), BT, 0, s>>>(nrows, rp, ci, v, next, Tci, Tv);
+}
+void launch_transpose_sort(int64_t ncols, const int32_t *Trp, int32_t *Tci, double *Tv, hipStream_t s) {
+    if (ncols > 0) k_transpose_sort<<<nblocks(ncols, BT), BT, 0, s>>>(ncols, Trp, Tci, Tv);
+}
+void launch_strength(int pass, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
+                     int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag, hipStream_t s) {
+    if (n <= 0) return;
+    if (pass == 0)
+        k_strength<false><<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag);
+    else
+        k_strength<true><<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag);
+}
+void launch_pmis_init(int64_t n, const int32_t *STrp, int32_t *state, hipStream_t s) {
+    if (n > 0) k_pmis_init<<<nblocks(n, BT), BT, 0, s>>>(n, STrp, state);
+}
+void launch_pmis_select(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *STrp, const int32_t *STci,
+                        const int32_t *state, uint64_t seed, int32_t *newc, hipStream_t s) {
+    if (n > 0) k_pmis_select<<<nblocks(n, BT), BT, 0, s>>>(n, Srp, Sci, STrp, STci, state, seed, newc);
+}
+void launch_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *newc, int32_t *state,
+                        int *counters, hipStream_t s) {
+    if (n > 0) k_pmis_update<<<nblocks(n, BT), BT, 0, s>>>(n, Srp, Sci, newc, state, counters);
+}
+void launch_cf_flags(int64_t n, const int32_t *state, int32_t *isC, hipStream_t s) {
+    if (n > 0) k_cf_flags<<<nblocks(n, BT), BT, 0, s>>>(n, state, isC);
+}
+void launch_interp_count(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *sflag, const int32_t *cf,
+                         int32_t *cnt, hipStream_t s) {
+    if (n > 0) k_interp_count<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, sflag, cf, cnt);
+}
+void launch_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *sflag,
+                        const int32_t *cf, const int32_t *cmap, const int32_t *Prp, int32_t *Pci, double *Pv,
+                        hipStream_t s) {
+    if (n > 0) k_interp_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp, Pci, Pv);
+}
+void launch_l1(int64_t n, const int32_t *rp, const double *v, double *l1, int *err, hipStream_t s) {
+    if (n > 0) k_l1<<<nblocks(n, BT), BT, 0, s>>>(n, rp, v, l1, err);
+}
+void launch_dense_lu(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *lu, int32_t *perm,
+                     int *err, hipStream_t s) {
+    if (n > 0) k_dense_lu<<<1, kLuBT, 0, s>>>(n, rp, ci, v, lu, perm, err);
+}
+void launch_pattern_outer(int64_t n, const int32_t *rp, const int32_t *ci, const double *lam, const double *x,
+                          double *d, hipStream_t s) {
+    if (n > 0) k_pattern_outer<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, lam, x, d);
+}
+
+}  // namespace mgr

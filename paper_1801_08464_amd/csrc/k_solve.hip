@@ -1,0 +1,288 @@
+// Solve-phase kernels: the fine-level SpMV on the cell-sliced ELL, CSR SpMV
+// variants for the coarser MGR levels, R, P and the AMG levels, the relaxations
+// of the MGR V-cycle and the coarsest dense solve.  Templated on the value type
+// (double, or float for the mixed-precision hierarchy).  Every row sum runs in
+// ascending column order per thread; the multi-lane CSR kernels reduce partial
+// sums across lanes, which reorders the additions only.
+#include "mgr_impl.h"
+
+namespace mgr {
+namespace {
+
+__device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// One wavefront per (slice, component): lane l owns row bs*(64 s + l) + v.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256) k_csell(int64_t ncell, int bs, int64_t npair, const int32_t *__restrict__ off,
+                                               const int32_t *__restrict__ width, const int32_t *__restrict__ col,
+                                               const T *__restrict__ val, const T *__restrict__ x,
+                                               const T *__restrict__ r, T *__restrict__ y) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (g >= npair) return;
+    const int64_t s = g / bs;
+    const int comp = (int)(g - s * bs);
+    const int64_t c = s * kWave + lane;
+    const int64_t o = off[g];
+    const int w = width[g];
+    const int32_t *cp = col + o * kWave + lane;
+    const T *vp = val + o * kWave + lane;
+    T acc = 0;
+#pragma unroll 4
+    for (int t = 0; t < w; ++t) {
+        const int j = __builtin_nontemporal_load(cp + (int64_t)t * kWave);
+        const T a = __builtin_nontemporal_load(vp + (int64_t)t * kWave);
+        if (j >= 0) acc = acc + a * x[j];
+    }
+    if (c < ncell) {
+        const int64_t i = c * bs + comp;
+        if (MODE == 0) y[i] = acc;
+        else if (MODE == 1) y[i] = r[i] - acc;
+        else y[i] = y[i] + acc;
+    }
+}
+
+// LANES threads per row; MODE 0: y = A x, 1: y = r - A x, 2: y += A x, 3: y = x + (r - A x) / d
+template <typename T, int LANES, int MODE>
+__global__ void __launch_bounds__(256) k_csr(int64_t nrows, const int32_t *__restrict__ rp,
+                                             const int32_t *__restrict__ ci, const T *__restrict__ v,
+                                             const T *__restrict__ x, const T *__restrict__ r,
+                                             const T *__restrict__ d, T *__restrict__ y) {
+    const int64_t gid = gtid();
+    const int64_t row = gid / LANES;
+    const int sub = (int)(gid % LANES);
+    T s = 0;
+    if (row < nrows) {
+        const int a = rp[row], b = rp[row + 1];
+        for (int p = a + sub; p < b; p += LANES) s = s + v[p] * x[ci[p]];
+    }
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
+    if (row < nrows && sub == 0) {
+        if (MODE == 0) y[row] = s;
+        else if (MODE == 1) y[row] = r[row] - s;
+        else if (MODE == 2) y[row] = y[row] + s;
+        else y[row] = x[row] + (r[row] - s) / d[row];
+    }
+}
+
+// t[f] = r[i] - (A e)[i] for the listed rows i = rows[f]
+template <typename T, int LANES>
+__global__ void __launch_bounds__(256) k_csr_rows_res(int64_t nr, const int32_t *__restrict__ rows,
+                                                      const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                      const T *__restrict__ v, const T *__restrict__ e,
+                                                      const T *__restrict__ r, T *__restrict__ t) {
+    const int64_t gid = gtid();
+    const int64_t f = gid / LANES;
+    const int sub = (int)(gid % LANES);
+    T s = 0;
+    int64_t i = 0;
+    if (f < nr) {
+        i = rows[f];
+        for (int p = rp[i] + sub; p < rp[i + 1]; p += LANES) s = s + v[p] * e[ci[p]];
+    }
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
+    if (f < nr && sub == 0) t[f] = r[i] - s;
+}
+
+// F-relaxation in place when A_FF is diagonal (no F row reads another F point)
+template <typename T, int LANES>
+__global__ void __launch_bounds__(256) k_frelax_inplace(int64_t nF, const int32_t *__restrict__ flist,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci, const T *__restrict__ v,
+                                                        const T *__restrict__ dinv, const T *__restrict__ r,
+                                                        T *e) {
+    const int64_t gid = gtid();
+    const int64_t f = gid / LANES;
+    const int sub = (int)(gid % LANES);
+    T s = 0;
+    int64_t i = 0;
+    if (f < nF) {
+        i = flist[f];
+        for (int p = rp[i] + sub; p < rp[i + 1]; p += LANES) s = s + v[p] * e[ci[p]];
+    }
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
+    if (f < nF && sub == 0) e[i] = e[i] + dinv[f] * (r[i] - s);
+}
+
+template <typename T>
+__global__ void k_block_apply3(int64_t ncell, const T *__restrict__ B, const T *__restrict__ r, T *__restrict__ e) {
+    const int64_t c = gtid();
+    if (c >= ncell) return;
+    const T r0 = r[3 * c], r1 = r[3 * c + 1], r2 = r[3 * c + 2];
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        e[3 * c + q] = B[(3 * q) * ncell + c] * r0 + B[(3 * q + 1) * ncell + c] * r1 + B[(3 * q + 2) * ncell + c] * r2;
+}
+
+template <typename T>
+__global__ void k_block_apply1(int64_t ncell, const T *__restrict__ B, const T *__restrict__ r, T *__restrict__ e) {
+    const int64_t c = gtid();
+    if (c < ncell) e[c] = B[c] * r[c];
+}
+
+template <typename T>
+__global__ void k_frelax_first(int64_t n, const int32_t *__restrict__ fmap, const T *__restrict__ dinv,
+                               const T *__restrict__ r, T *__restrict__ e) {
+    const int64_t i = gtid();
+    if (i >= n) return;
+    const int f = fmap[i];
+    e[i] = f >= 0 ? dinv[f] * r[i] : (T)0;
+}
+
+template <typename T>
+__global__ void k_frelax_scatter(int64_t nF, const int32_t *__restrict__ flist, const T *__restrict__ dinv,
+                                 const T *__restrict__ t, T *__restrict__ e) {
+    const int64_t f = gtid();
+    if (f >= nF) return;
+    const int64_t i = flist[f];
+    e[i] = e[i] + dinv[f] * t[f];
+}
+
+template <typename T>
+__global__ void k_div(int64_t n, const T *__restrict__ r, const T *__restrict__ d, T *__restrict__ x) {
+    const int64_t i = gtid();
+    if (i < n) x[i] = r[i] / d[i];
+}
+
+// forward/back substitution with the coarsest LU (FP64 throughout); one workgroup
+template <typename T>
+__global__ void __launch_bounds__(256) k_lu_solve(int64_t n, const double *__restrict__ lu,
+                                                  const int32_t *__restrict__ perm, const T *__restrict__ b,
+                                                  T *__restrict__ x) {
+    extern __shared__ double y[];
+    const int tid = threadIdx.x;
+    for (int64_t i = tid; i < n; i += blockDim.x) y[i] = (double)b[perm[i]];
+    __syncthreads();
+    for (int64_t k = 0; k < n; ++k) {
+        const double yk = y[k];
+        for (int64_t i = k + 1 + tid; i < n; i += blockDim.x) y[i] = y[i] - lu[i * n + k] * yk;
+        __syncthreads();
+    }
+    for (int64_t k = n - 1; k >= 0; --k) {
+        if (tid == 0) y[k] = y[k] / lu[k * n + k];
+        __syncthreads();
+        const double yk = y[k];
+        for (int64_t i = tid; i < k; i += blockDim.x) y[i] = y[i] - lu[i * n + k] * yk;
+        __syncthreads();
+    }
+    for (int64_t i = tid; i < n; i += blockDim.x) x[i] = (T)y[i];
+}
+
+}  // namespace
+
+constexpr int BT = 256;
+
+template <typename T>
+void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s) {
+    int64_t npair = A.nslice * A.bs;
+    if (npair <= 0) return;
+    unsigned g = nblocks(npair, BT / kWave);
+    if (mode == 0) k_csell<T, 0><<<g, BT, 0, s>>>(A.ncell, A.bs, npair, A.off, A.width, A.col, vals, x, r, y);
+    else if (mode == 1) k_csell<T, 1><<<g, BT, 0, s>>>(A.ncell, A.bs, npair, A.off, A.width, A.col, vals, x, r, y);
+    else k_csell<T, 2><<<g, BT, 0, s>>>(A.ncell, A.bs, npair, A.off, A.width, A.col, vals, x, r, y);
+}
+
+template <typename T, int LANES>
+static void csr_mode(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y,
+                     hipStream_t s) {
+    unsigned g = nblocks(A.nrows * LANES, BT);
+    switch (mode) {
+    case 0: k_csr<T, LANES, 0><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 1: k_csr<T, LANES, 1><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 2: k_csr<T, LANES, 2><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    default: k_csr<T, LANES, 3><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    }
+}
+
+template <typename T>
+void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
+    if (A.nrows <= 0) return;
+    switch (A.lanes) {
+    case 1: csr_mode<T, 1>(mode, A, vals, x, r, d, y, s); break;
+    case 2: csr_mode<T, 2>(mode, A, vals, x, r, d, y, s); break;
+    case 4: csr_mode<T, 4>(mode, A, vals, x, r, d, y, s); break;
+    case 8: csr_mode<T, 8>(mode, A, vals, x, r, d, y, s); break;
+    case 16: csr_mode<T, 16>(mode, A, vals, x, r, d, y, s); break;
+    default: csr_mode<T, 32>(mode, A, vals, x, r, d, y, s); break;
+    }
+}
+
+template <typename T>
+void launch_csr_rows_residual(const DCsr &A, const T *vals, int64_t nrows, const int32_t *rows, const T *e,
+                              const T *r, T *t, hipStream_t s) {
+    if (nrows <= 0) return;
+    int L = A.lanes;
+    unsigned g = nblocks(nrows * L, BT);
+    switch (L) {
+    case 1: k_csr_rows_res<T, 1><<<g, BT, 0, s>>>(nrows, rows, A.rp, A.ci, vals, e, r, t); break;
+    case 2: k_csr_rows_res<T, 2><<<g, BT, 0, s>>>(nrows, rows, A.rp, A.ci, vals, e, r, t); break;
+    case 4: k_csr_rows_res<T, 4><<<g, BT, 0, s>>>(nrows, rows, A.rp, A.ci, vals, e, r, t); break;
+    case 8: k_csr_rows_res<T, 8><<<g, BT, 0, s>>>(nrows, rows, A.rp, A.ci, vals, e, r, t); break;
+    case 16: k_csr_rows_res<T, 16><<<g, BT, 0, s>>>(nrows, rows, A.rp, A.ci, vals, e, r, t); break;
+    default: k_csr_rows_res<T, 32><<<g, BT, 0, s>>>(nrows, rows, A.rp, A.ci, vals, e, r, t); break;
+    }
+}
+
+template <typename T>
+void launch_frelax_inplace(const DCsr &A, const T *vals, int64_t nF, const int32_t *flist, const T *dinv,
+                           const T *r, T *e, hipStream_t s) {
+    if (nF <= 0) return;
+    int L = A.lanes;
+    unsigned g = nblocks(nF * L, BT);
+    switch (L) {
+    case 1: k_frelax_inplace<T, 1><<<g, BT, 0, s>>>(nF, flist, A.rp, A.ci, vals, dinv, r, e); break;
+    case 2: k_frelax_inplace<T, 2><<<g, BT, 0, s>>>(nF, flist, A.rp, A.ci, vals, dinv, r, e); break;
+    case 4: k_frelax_inplace<T, 4><<<g, BT, 0, s>>>(nF, flist, A.rp, A.ci, vals, dinv, r, e); break;
+    case 8: k_frelax_inplace<T, 8><<<g, BT, 0, s>>>(nF, flist, A.rp, A.ci, vals, dinv, r, e); break;
+    case 16: k_frelax_inplace<T, 16><<<g, BT, 0, s>>>(nF, flist, A.rp, A.ci, vals, dinv, r, e); break;
+    default: k_frelax_inplace<T, 32><<<g, BT, 0, s>>>(nF, flist, A.rp, A.ci, vals, dinv, r, e); break;
+    }
+}
+
+template <typename T>
+void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, hipStream_t s) {
+    if (ncell <= 0) return;
+    if (bs == 3) k_block_apply3<T><<<nblocks(ncell, BT), BT, 0, s>>>(ncell, binv, r, e);
+    else k_block_apply1<T><<<nblocks(ncell, BT), BT, 0, s>>>(ncell, binv, r, e);
+}
+
+template <typename T>
+void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T *r, T *e, hipStream_t s) {
+    if (n > 0) k_frelax_first<T><<<nblocks(n, BT), BT, 0, s>>>(n, fmap, dinv, r, e);
+}
+
+template <typename T>
+void launch_frelax_scatter(int64_t nF, const int32_t *flist, const T *dinv, const T *t, T *e, hipStream_t s) {
+    if (nF > 0) k_frelax_scatter<T><<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, dinv, t, e);
+}
+
+template <typename T>
+void launch_div(int64_t n, const T *r, const T *d, T *x, hipStream_t s) {
+    if (n > 0) k_div<T><<<nblocks(n, BT), BT, 0, s>>>(n, r, d, x);
+}
+
+template <typename T>
+void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s) {
+    if (n > 0) k_lu_solve<T><<<1, BT, (size_t)n * sizeof(double), s>>>(n, lu, perm, b, x);
+}
+
+#define MGR_INSTANTIATE(T)                                                                                      \
+    template void launch_csell<T>(int, const CSell &, const T *, const T *, const T *, T *, hipStream_t);       \
+    template void launch_csr<T>(int, const DCsr &, const T *, const T *, const T *, const T *, T *, hipStream_t); \
+    template void launch_csr_rows_residual<T>(const DCsr &, const T *, int64_t, const int32_t *, const T *,      \
+                                              const T *, T *, hipStream_t);                                     \
+    template void launch_frelax_inplace<T>(const DCsr &, const T *, int64_t, const int32_t *, const T *,        \
+                                           const T *, T *, hipStream_t);                                        \
+    template void launch_block_apply<T>(int64_t, int, const T *, const T *, T *, hipStream_t);                  \
+    template void launch_frelax_first<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);     \
+    template void launch_frelax_scatter<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);   \
+    template void launch_div<T>(int64_t, const T *, const T *, T *, hipStream_t);                               \
+    template void launch_lu_solve<T>(int64_t, const double *, const int32_t *, const T *, T *, hipStream_t);
+
+MGR_INSTANTIATE(double)
+MGR_INSTANTIATE(float)
+
+}  // namespace mgr

@@ -1,0 +1,1012 @@
+// Host orchestration of libmgr and its C ABI: hierarchy setup (every step a
+// GPU kernel; the host only reads back sizes and status words), the recursive
+// MGR V-cycle and the restarted GMRES driver.
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "mgr_impl.h"
+
+using namespace mgr;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+    int code;
+};
+
+#define HIPCHK(x)                                                                                    \
+    do {                                                                                             \
+        hipError_t e_ = (x);                                                                         \
+        if (e_ != hipSuccess) throw_err(h, MGR_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+[[noreturn]] void throw_err(mgr_handle *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    g_err = msg;
+    throw Fail{code};
+}
+
+void sync(mgr_handle *h) { HIPCHK(hipStreamSynchronize(h->stream)); }
+
+template <typename T>
+T *dalloc(mgr_handle *h, int64_t n) {
+    T *p = nullptr;
+    if (alloc_n(h, &p, n) != MGR_OK) throw_err(h, MGR_E_OOM, "device allocation failed");
+    return p;
+}
+
+// temporary device buffer released at scope exit
+template <typename T>
+struct Tmp {
+    T *p = nullptr;
+    hipStream_t s = nullptr;
+    Tmp(mgr_handle *h, int64_t n) : s(h->stream) {
+        if (hipMalloc(reinterpret_cast<void **>(&p), (size_t)(n > 0 ? n : 1) * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            throw_err(h, MGR_E_OOM, "device allocation failed (temporary)");
+        }
+    }
+    ~Tmp() {
+        if (p) {
+            (void)hipStreamSynchronize(s);  // queued kernels may still read or write it
+            (void)hipFree(p);
+        }
+    }
+    Tmp(const Tmp &) = delete;
+    Tmp &operator=(const Tmp &) = delete;
+};
+
+template <typename T>
+T d2h1(mgr_handle *h, const T *p) {
+    T v;
+    HIPCHK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+    return v;
+}
+
+void reset_err(mgr_handle *h) {
+    int init[8] = {0, 0, 0, INT_MAX, 0, 0, 0, 0};
+    std::memcpy(h->herr, init, sizeof init);
+    HIPCHK(hipMemcpyAsync(h->derr, h->herr, sizeof init, hipMemcpyHostToDevice, h->stream));
+}
+
+void read_err(mgr_handle *h) {
+    HIPCHK(hipMemcpyAsync(h->herr, h->derr, 8 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+}
+
+// exclusive scan of n counts into out[0..n]; returns the total (checked to fit int32)
+int64_t scan(mgr_handle *h, const int32_t *in, int32_t *out, int64_t n) {
+    Tmp<int64_t> tmp(h, scan_tmp_words(n));
+    launch_scan(in, out, n, tmp.p, h->stream);
+    int64_t nt = (n + 2047) / 2048;
+    int64_t total = n > 0 ? d2h1(h, tmp.p + nt) : 0;
+    if (total > INT_MAX) throw_err(h, MGR_E_INVALID, "a hierarchy matrix exceeds 2^31-1 entries");
+    return total;
+}
+
+int choose_lanes(const DCsr &A) {
+    double avg = A.nrows > 0 ? (double)A.nnz / (double)A.nrows : 0.0;
+    if (avg < 2) return 1;
+    if (avg < 4) return 2;
+    if (avg < 8) return 4;
+    if (avg < 16) return 8;
+    if (avg < 40) return 16;
+    return 32;
+}
+
+DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B) {
+    DCsr C;
+    C.nrows = A.nrows;
+    C.ncols = B.ncols;
+    Tmp<int32_t> cnt(h, A.nrows);
+    reset_err(h);
+    launch_spgemm(0, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6, h->stream);
+    C.rp = dalloc<int32_t>(h, A.nrows + 1);
+    C.nnz = scan(h, cnt.p, C.rp, A.nrows);
+    read_err(h);
+    if (h->herr[6])
+        throw_err(h, MGR_E_INVALID,
+                  "SpGEMM: a left-operand row exceeds " + std::to_string(spgemm_max_row()) + " entries");
+    C.ci = dalloc<int32_t>(h, C.nnz);
+    C.v = dalloc<double>(h, C.nnz);
+    launch_spgemm(1, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v, h->derr + 6, h->stream);
+    return C;
+}
+
+DCsr transpose(mgr_handle *h, const DCsr &A, bool values) {
+    DCsr T;
+    T.nrows = A.ncols;
+    T.ncols = A.nrows;
+    Tmp<int32_t> cnt(h, A.ncols);
+    launch_fill_i32(cnt.p, 0, A.ncols, h->stream);
+    launch_transpose_count(A.nrows, A.rp, A.ci, cnt.p, h->stream);
+    T.rp = dalloc<int32_t>(h, A.ncols + 1);
+    T.nnz = scan(h, cnt.p, T.rp, A.ncols);
+    T.ci = dalloc<int32_t>(h, T.nnz);
+    if (values) T.v = dalloc<double>(h, T.nnz);
+    HIPCHK(hipMemcpyAsync(cnt.p, T.rp, A.ncols * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+    launch_transpose_fill(A.nrows, A.rp, A.ci, values ? A.v : nullptr, cnt.p, T.ci, T.v, h->stream);
+    launch_transpose_sort(A.ncols, T.rp, T.ci, T.v, h->stream);
+    sync(h);
+    return T;
+}
+
+void build_csell(mgr_handle *h) {
+    CSell &S = h->A0s;
+    const DCsr &A = h->A0;
+    S.bs = h->bs;
+    S.ncell = h->ncell;
+    S.nslice = (h->ncell + kWave - 1) / kWave;
+    S.nnz_true = A.nnz;
+    int64_t npair = S.nslice * S.bs;
+    Tmp<int32_t> rowlen(h, A.nrows);
+    launch_csell_count(h->ncell, h->bs, A.rp, rowlen.p, h->stream);
+    S.width = dalloc<int32_t>(h, npair);
+    launch_csell_width(S.nslice, S.bs, S.ncell, rowlen.p, S.width, h->stream);
+    S.off = dalloc<int32_t>(h, npair + 1);
+    S.nslot = scan(h, S.width, S.off, npair);
+    S.col = dalloc<int32_t>(h, S.nslot * kWave);
+    S.v = dalloc<double>(h, S.nslot * kWave);
+    launch_fill_i32(S.col, -1, S.nslot * kWave, h->stream);
+    launch_fill_f64(S.v, 0.0, S.nslot * kWave, h->stream);
+    launch_csell_fill(S.ncell, S.bs, A.rp, A.ci, A.v, S.off, S.width, S.col, S.v, h->stream);
+}
+
+void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int32_t *&glob_next) {
+    MgrLevel &lv = h->lev[l];
+    const DCsr &A = lv.A;
+    const int64_t n = A.nrows;
+    lv.n = n;
+    Tmp<int32_t> isF(h, n), isC(h, n), fpos(h, n + 1), cpos(h, n + 1), cmap(h, n);
+    launch_level_flags(n, lv.lab, l, isF.p, isC.p, h->stream);
+    lv.nF = scan(h, isF.p, fpos.p, n);
+    lv.nC = scan(h, isC.p, cpos.p, n);
+    if (lv.nC == 0) throw_err(h, MGR_E_INVALID, "MGR level " + std::to_string(l) + " has no coarse points");
+    lv.fmap = dalloc<int32_t>(h, n);
+    lv.flist = dalloc<int32_t>(h, lv.nF);
+    lv.clist = dalloc<int32_t>(h, lv.nC);
+    launch_level_maps(n, lv.lab, l, fpos.p, cpos.p, lv.fmap, cmap.p, lv.flist, lv.clist, h->stream);
+    lv.dinv = dalloc<double>(h, lv.nF);
+    reset_err(h);
+    launch_fdiag_inverse(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.dinv, h->derr, h->derr + 5, lv.fmap, h->stream);
+    read_err(h);
+    if (h->herr[3] != INT_MAX) {
+        int row = h->herr[3];
+        int g = d2h1(h, lv.glob + row);
+        char msg[200];
+        std::snprintf(msg, sizeof msg, "MGR level %d: zero diagonal at F row %d (global unknown %d)", l, row, g);
+        throw_err(h, MGR_E_ZERO_FDIAG, msg);
+    }
+    lv.aff_diag = h->herr[5] == 0;
+    const int rp_type = h->o.rp_type;
+    // P = [W_p; I]
+    {
+        Tmp<int32_t> cnt(h, n);
+        launch_p_count(n, A.rp, A.ci, cmap.p, rp_type, cnt.p, h->stream);
+        lv.P.nrows = n;
+        lv.P.ncols = lv.nC;
+        lv.P.rp = dalloc<int32_t>(h, n + 1);
+        lv.P.nnz = scan(h, cnt.p, lv.P.rp, n);
+        lv.P.ci = dalloc<int32_t>(h, lv.P.nnz);
+        lv.P.v = dalloc<double>(h, lv.P.nnz);
+        launch_p_fill(n, A.rp, A.ci, A.v, cmap.p, lv.fmap, lv.dinv, rp_type, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
+    }
+    // R = [W_r, I]
+    {
+        Tmp<int32_t> cnt(h, lv.nC);
+        launch_r_count(lv.nC, lv.clist, A.rp, A.ci, lv.fmap, rp_type, cnt.p, h->stream);
+        lv.R.nrows = lv.nC;
+        lv.R.ncols = n;
+        lv.R.rp = dalloc<int32_t>(h, lv.nC + 1);
+        lv.R.nnz = scan(h, cnt.p, lv.R.rp, lv.nC);
+        lv.R.ci = dalloc<int32_t>(h, lv.R.nnz);
+        lv.R.v = dalloc<double>(h, lv.R.nnz);
+        launch_r_fill(lv.nC, lv.clist, A.rp, A.ci, A.v, lv.fmap, lv.dinv, rp_type, lv.R.rp, lv.R.ci, lv.R.v,
+                      h->stream);
+    }
+    // A_{l+1} = R (A P)
+    {
+        DCsr T = spgemm(h, A, lv.P);
+        Anext = spgemm(h, lv.R, T);
+        sync(h);
+        (void)hipFree(T.rp);
+        (void)hipFree(T.ci);
+        (void)hipFree(T.v);
+        // T's buffers were registered with the handle; drop them from the list
+        for (auto &p : h->allocs)
+            if (p == T.rp || p == T.ci || p == T.v) p = nullptr;
+    }
+    lab_next = dalloc<int32_t>(h, lv.nC);
+    glob_next = dalloc<int32_t>(h, lv.nC);
+    launch_gather_i32(lv.nC, lv.clist, lv.lab, lab_next, h->stream);
+    launch_gather_i32(lv.nC, lv.clist, lv.glob, glob_next, h->stream);
+}
+
+void build_amg(mgr_handle *h, const DCsr &Atop) {
+    const mgr_options &o = h->o;
+    DCsr A = Atop;
+    for (int k = 0;; ++k) {
+        h->amg.emplace_back();
+        AmgLevel &lv = h->amg.back();
+        lv.A = A;
+        lv.n = A.nrows;
+        const int64_t n = A.nrows;
+        bool coarsest = n <= o.amg_coarse_max || k == o.amg_max_levels - 1;
+        if (!coarsest) {
+            // strength of connection
+            Tmp<int32_t> cnt(h, n);
+            Tmp<uint8_t> sflag(h, A.nnz);
+            launch_strength(0, n, A.rp, A.ci, A.v, o.amg_theta, cnt.p, nullptr, nullptr, h->stream);
+            lv.S.nrows = n;
+            lv.S.ncols = n;
+            lv.S.rp = dalloc<int32_t>(h, n + 1);
+            lv.S.nnz = scan(h, cnt.p, lv.S.rp, n);
+            lv.S.ci = dalloc<int32_t>(h, lv.S.nnz);
+            launch_strength(1, n, A.rp, A.ci, A.v, o.amg_theta, lv.S.rp, lv.S.ci, sflag.p, h->stream);
+            DCsr ST = transpose(h, lv.S, false);
+            // PMIS
+            lv.cf = dalloc<int32_t>(h, n);
+            Tmp<int32_t> newc(h, n);
+            launch_pmis_init(n, ST.rp, lv.cf, h->stream);
+            for (int round = 0;; ++round) {
+                reset_err(h);
+                launch_pmis_select(n, lv.S.rp, lv.S.ci, ST.rp, ST.ci, lv.cf, o.pmis_seed, newc.p, h->stream);
+                launch_pmis_update(n, lv.S.rp, lv.S.ci, newc.p, lv.cf, h->derr + 6, h->stream);
+                read_err(h);
+                if (h->herr[6] == 0) break;
+                if (h->herr[7] == 0 || round > 100000) throw_err(h, MGR_E_INVALID, "PMIS made no progress");
+            }
+            (void)hipFree(ST.rp);
+            (void)hipFree(ST.ci);
+            for (auto &p : h->allocs)
+                if (p == ST.rp || p == ST.ci) p = nullptr;
+            Tmp<int32_t> isC(h, n), cmap(h, n + 1);
+            launch_cf_flags(n, lv.cf, isC.p, h->stream);
+            const int64_t nc = scan(h, isC.p, cmap.p, n);
+            if (nc == 0 || nc == n || (double)nc > 0.9 * (double)n) {
+                coarsest = true;
+            } else {
+                lv.nc = nc;
+                launch_interp_count(n, A.rp, A.ci, sflag.p, lv.cf, cnt.p, h->stream);
+                lv.P.nrows = n;
+                lv.P.ncols = nc;
+                lv.P.rp = dalloc<int32_t>(h, n + 1);
+                lv.P.nnz = scan(h, cnt.p, lv.P.rp, n);
+                lv.P.ci = dalloc<int32_t>(h, lv.P.nnz);
+                lv.P.v = dalloc<double>(h, lv.P.nnz);
+                launch_interp_fill(n, A.rp, A.ci, A.v, sflag.p, lv.cf, cmap.p, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
+                lv.PT = transpose(h, lv.P, true);
+                DCsr T = spgemm(h, A, lv.P);
+                DCsr Ac = spgemm(h, lv.PT, T);
+                sync(h);
+                (void)hipFree(T.rp);
+                (void)hipFree(T.ci);
+                (void)hipFree(T.v);
+                for (auto &p : h->allocs)
+                    if (p == T.rp || p == T.ci || p == T.v) p = nullptr;
+                lv.l1 = dalloc<double>(h, n);
+                reset_err(h);
+                launch_l1(n, A.rp, A.v, lv.l1, h->derr, h->stream);
+                read_err(h);
+                if (h->herr[3] != INT_MAX)
+                    throw_err(h, MGR_E_SINGULAR_BLOCK,
+                              "AMG level " + std::to_string(k) + ": empty row " + std::to_string(h->herr[3]));
+                A = Ac;
+                continue;
+            }
+        }
+        // coarsest level: dense LU
+        if (n > o.dense_max)
+            throw_err(h, MGR_E_INVALID, "AMG coarsening stalled at " + std::to_string(n) +
+                                            " unknowns, above the dense coarse-solve limit");
+        h->ncoarse = n;
+        h->lu = dalloc<double>(h, n * n);
+        h->perm = dalloc<int32_t>(h, n);
+        reset_err(h);
+        launch_dense_lu(n, A.rp, A.ci, A.v, h->lu, h->perm, h->derr, h->stream);
+        read_err(h);
+        if (h->herr[4]) throw_err(h, MGR_E_SINGULAR_BLOCK, "AMG: coarsest matrix is singular");
+        return;
+    }
+}
+
+float *to_f32(mgr_handle *h, const double *v, int64_t n) {
+    float *f = dalloc<float>(h, n);
+    launch_cast_f64_f32(v, f, n, h->stream);
+    return f;
+}
+
+void alloc_work(mgr_handle *h) {
+    const bool mixed = h->o.precision == 1;
+    for (size_t l = 0; l < h->lev.size(); ++l) {
+        MgrLevel &lv = h->lev[l];
+        if (mixed) {
+            lv.rf = dalloc<float>(h, lv.n);
+            lv.ef = dalloc<float>(h, lv.n);
+            lv.tf = dalloc<float>(h, lv.n);
+        } else {
+            lv.r = dalloc<double>(h, lv.n);
+            lv.e = dalloc<double>(h, lv.n);
+            lv.t = dalloc<double>(h, lv.n);
+        }
+    }
+    for (auto &lv : h->amg) {
+        if (mixed) {
+            lv.rf = dalloc<float>(h, lv.n);
+            lv.xf = dalloc<float>(h, lv.n);
+            lv.x2f = dalloc<float>(h, lv.n);
+            lv.tf = dalloc<float>(h, lv.n);
+        } else {
+            lv.r = dalloc<double>(h, lv.n);
+            lv.x = dalloc<double>(h, lv.n);
+            lv.x2 = dalloc<double>(h, lv.n);
+            lv.t = dalloc<double>(h, lv.n);
+        }
+    }
+}
+
+void to_mixed(mgr_handle *h) {
+    if (h->binv) h->binvf = to_f32(h, h->binv, h->ncell * h->bs * h->bs);
+    h->A0s.vf = to_f32(h, h->A0s.v, h->A0s.nslot * kWave);
+    for (auto &lv : h->lev) {
+        lv.A.vf = to_f32(h, lv.A.v, lv.A.nnz);
+        lv.P.vf = to_f32(h, lv.P.v, lv.P.nnz);
+        lv.R.vf = to_f32(h, lv.R.v, lv.R.nnz);
+        lv.dinvf = to_f32(h, lv.dinv, lv.nF);
+    }
+    for (size_t k = 0; k + 1 < h->amg.size(); ++k) {
+        AmgLevel &lv = h->amg[k];
+        lv.A.vf = to_f32(h, lv.A.v, lv.A.nnz);
+        lv.P.vf = to_f32(h, lv.P.v, lv.P.nnz);
+        lv.PT.vf = to_f32(h, lv.PT.v, lv.PT.nnz);
+        lv.l1f = to_f32(h, lv.l1, lv.n);
+    }
+}
+
+// ---------------- V-cycle ----------------
+template <typename T>
+struct P_;
+template <>
+struct P_<double> {
+    static const double *v(const DCsr &A) { return A.v; }
+    static const double *v(const CSell &A) { return A.v; }
+    static const double *binv(const mgr_handle *h) { return h->binv; }
+    static const double *dinv(const MgrLevel &l) { return l.dinv; }
+    static const double *l1(const AmgLevel &l) { return l.l1; }
+    static double *r(MgrLevel &l) { return l.r; }
+    static double *e(MgrLevel &l) { return l.e; }
+    static double *t(MgrLevel &l) { return l.t; }
+    static double *r(AmgLevel &l) { return l.r; }
+    static double *x(AmgLevel &l) { return l.x; }
+    static double *x2(AmgLevel &l) { return l.x2; }
+    static double *t(AmgLevel &l) { return l.t; }
+    static void fill(double *p, int64_t n, hipStream_t s) { launch_fill_f64(p, 0.0, n, s); }
+};
+template <>
+struct P_<float> {
+    static const float *v(const DCsr &A) { return A.vf; }
+    static const float *v(const CSell &A) { return A.vf; }
+    static const float *binv(const mgr_handle *h) { return h->binvf; }
+    static const float *dinv(const MgrLevel &l) { return l.dinvf; }
+    static const float *l1(const AmgLevel &l) { return l.l1f; }
+    static float *r(MgrLevel &l) { return l.rf; }
+    static float *e(MgrLevel &l) { return l.ef; }
+    static float *t(MgrLevel &l) { return l.tf; }
+    static float *r(AmgLevel &l) { return l.rf; }
+    static float *x(AmgLevel &l) { return l.xf; }
+    static float *x2(AmgLevel &l) { return l.x2f; }
+    static float *t(AmgLevel &l) { return l.tf; }
+    static void fill(float *p, int64_t n, hipStream_t s) { launch_fill_f32(p, 0.0f, n, s); }
+};
+
+// the fine-level sliced-ELL kernel, optionally bracketed by events for timing
+template <typename T>
+void fine_op(mgr_handle *h, int mode, const T *x, const T *r, T *y) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->timing) {
+        while (h->ev.size() < h->ev_used + 2) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            h->ev.push_back(e);
+        }
+        e0 = h->ev[h->ev_used];
+        e1 = h->ev[h->ev_used + 1];
+        h->ev_used += 2;
+        HIPCHK(hipEventRecord(e0, h->stream));
+    }
+    launch_csell<T>(mode, h->A0s, P_<T>::v(h->A0s), x, r, y, h->stream);
+    if (h->timing) {
+        HIPCHK(hipEventRecord(e1, h->stream));
+        // algorithmic bytes: values + columns of the true nonzeros, row pointers,
+        // x and y, plus r for the residual form
+        const double n = (double)h->n;
+        h->t_bytes += (double)h->A0s.nnz_true * (sizeof(T) + 4.0) + 4.0 * (n + 1) + 2.0 * n * sizeof(T) +
+                      (mode == 1 ? n * sizeof(T) : 0.0);
+        h->t_launches++;
+    }
+}
+
+template <typename T>
+void amg_cycle(mgr_handle *h, int k, const T *r, T *x) {
+    AmgLevel &lv = h->amg[k];
+    hipStream_t s = h->stream;
+    const int64_t n = lv.n;
+    if (k == (int)h->amg.size() - 1) {
+        launch_lu_solve<T>(n, h->lu, h->perm, r, x, s);
+        return;
+    }
+    const T *Av = P_<T>::v(lv.A);
+    const T *l1 = P_<T>::l1(lv);
+    const int pre = h->o.amg_pre, post = h->o.amg_post;
+    // ping-pong buffers arranged so that the last sweep writes x
+    const int swaps = (pre > 0 ? pre - 1 : 0) + post;
+    T *cur = (swaps % 2 == 0) ? x : P_<T>::x2(lv);
+    T *oth = (cur == x) ? P_<T>::x2(lv) : x;
+    for (int it = 0; it < pre; ++it) {
+        if (it == 0) {
+            launch_div<T>(n, r, l1, cur, s);
+        } else {
+            launch_csr<T>(3, lv.A, Av, cur, r, l1, oth, s);
+            std::swap(cur, oth);
+        }
+    }
+    if (pre == 0) P_<T>::fill(cur, n, s);
+    T *t = P_<T>::t(lv);
+    launch_csr<T>(1, lv.A, Av, cur, r, nullptr, t, s);
+    AmgLevel &nx = h->amg[k + 1];
+    launch_csr<T>(0, lv.PT, P_<T>::v(lv.PT), t, nullptr, nullptr, P_<T>::r(nx), s);
+    amg_cycle<T>(h, k + 1, P_<T>::r(nx), P_<T>::x(nx));
+    launch_csr<T>(2, lv.P, P_<T>::v(lv.P), P_<T>::x(nx), nullptr, nullptr, cur, s);
+    for (int it = 0; it < post; ++it) {
+        launch_csr<T>(3, lv.A, Av, cur, r, l1, oth, s);
+        std::swap(cur, oth);
+    }
+}
+
+template <typename T>
+void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
+    if (l == h->L) {
+        amg_cycle<T>(h, 0, r, e);
+        return;
+    }
+    MgrLevel &lv = h->lev[l];
+    hipStream_t s = h->stream;
+    const T *Av = P_<T>::v(lv.A);
+    const T *dinv = P_<T>::dinv(lv);
+    T *t = P_<T>::t(lv);
+    bool have = false;
+    if (l == 0 && h->o.global_relax) {
+        launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), r, e, s);
+        have = true;
+    }
+    for (int sw = 0; sw < h->o.f_sweeps; ++sw) {
+        if (!have) {
+            launch_frelax_first<T>(lv.n, lv.fmap, dinv, r, e, s);
+            have = true;
+        } else if (lv.aff_diag) {
+            launch_frelax_inplace<T>(lv.A, Av, lv.nF, lv.flist, dinv, r, e, s);
+        } else {
+            launch_csr_rows_residual<T>(lv.A, Av, lv.nF, lv.flist, e, r, t, s);
+            launch_frelax_scatter<T>(lv.nF, lv.flist, dinv, t, e, s);
+        }
+    }
+    if (!have) P_<T>::fill(e, lv.n, s);
+    if (l == 0) fine_op<T>(h, 1, e, r, t);
+    else launch_csr<T>(1, lv.A, Av, e, r, nullptr, t, s);
+    T *rc, *ec;
+    if (l + 1 < h->L) {
+        rc = P_<T>::r(h->lev[l + 1]);
+        ec = P_<T>::e(h->lev[l + 1]);
+    } else {
+        rc = P_<T>::r(h->amg[0]);
+        ec = P_<T>::x(h->amg[0]);
+    }
+    launch_csr<T>(0, lv.R, P_<T>::v(lv.R), t, nullptr, nullptr, rc, s);
+    mgr_cycle<T>(h, l + 1, rc, ec);
+    launch_csr<T>(2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e, s);
+}
+
+void apply_prec(mgr_handle *h, const double *v, double *z) {
+    if (h->o.precision == 1) {
+        float *rf = h->L > 0 ? h->lev[0].rf : h->amg[0].rf;
+        float *ef = h->L > 0 ? h->lev[0].ef : h->amg[0].xf;
+        launch_cast_f64_f32(v, rf, h->n, h->stream);
+        mgr_cycle<float>(h, 0, rf, ef);
+        launch_cast_f32_f64(ef, z, h->n, h->stream);
+    } else {
+        mgr_cycle<double>(h, 0, v, z);
+    }
+}
+
+double dev_norm(mgr_handle *h, const double *a, double *out) {
+    launch_norm_part(h->n, a, h->part, h->stream);
+    launch_norm_fin(red_blocks(h->n), h->part, out, h->stream);
+    return d2h1(h, out);
+}
+
+int gmres(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) {
+    const int64_t n = h->n;
+    const int m = h->m;
+    hipStream_t s = h->stream;
+    double *dsc = h->dsc;
+    const int nblk = red_blocks(n);
+    int *guard = h->derr + 7;
+    int its = 0;
+    double rel = 0.0;
+    if (st) st->res_history_len = 0;
+    const double bnorm = dev_norm(h, b, dsc + Dsc::BNORM);
+    if (!std::isfinite(bnorm)) return MGR_E_BREAKDOWN;
+    if (!h->o.use_x0) launch_fill_f64(x, 0.0, n, s);
+    if (bnorm == 0.0) {
+        launch_fill_f64(x, 0.0, n, s);
+        sync(h);
+        if (st) {
+            st->iterations = 0;
+            st->rel_residual = 0.0;
+        }
+        return MGR_OK;
+    }
+    int status = MGR_NOT_CONVERGED;
+    for (;;) {
+        fine_op<double>(h, 1, x, b, h->res);
+        const double beta = dev_norm(h, h->res, dsc + Dsc::BETA);
+        rel = beta / bnorm;
+        if (!std::isfinite(beta)) {
+            status = MGR_E_BREAKDOWN;
+            break;
+        }
+        if (beta <= tol * bnorm) {
+            status = MGR_OK;
+            break;
+        }
+        if (its >= h->o.max_iter) {
+            status = MGR_NOT_CONVERGED;
+            break;
+        }
+        launch_scale_dev(n, h->res, dsc + Dsc::BETA, 1, h->V, s);
+        launch_fill_f64(dsc + Dsc::g(0, m), 0.0, m + 1, s);
+        HIPCHK(hipMemcpyAsync(dsc + Dsc::g(0, m), dsc + Dsc::BETA, sizeof(double), hipMemcpyDeviceToDevice, s));
+        int k = 0;
+        bool broke = false;
+        for (int j = 0; j < m; ++j) {
+            double *vj = h->V + (int64_t)j * n;
+            double *zj = h->Z + (int64_t)j * n;
+            apply_prec(h, vj, zj);
+            fine_op<double>(h, 0, zj, nullptr, h->w);
+            launch_mdot(n, j + 1, h->V, h->w, h->part, nullptr, s);
+            launch_arnoldi_fin(0, j, m, nblk, h->part, dsc, guard, s);
+            launch_maxpy_norm(n, j + 1, h->V, dsc + Dsc::hcur(0, m), h->w, h->part, nullptr, s);
+            launch_arnoldi_fin(1, j, m, nblk, h->part, dsc, guard, s);
+            launch_mdot(n, j + 1, h->V, h->w, h->part, guard, s);
+            launch_arnoldi_fin(2, j, m, nblk, h->part, dsc, guard, s);
+            launch_maxpy_norm(n, j + 1, h->V, dsc + Dsc::hcur(0, m), h->w, h->part, guard, s);
+            launch_arnoldi_fin(3, j, m, nblk, h->part, dsc, guard, s);
+            launch_givens(j, m, dsc, s);
+            HIPCHK(hipMemcpyAsync(h->hsc, dsc + Dsc::GABS, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            sync(h);
+            const double gabs = h->hsc[0], hn = h->hsc[1];
+            its++;
+            k = j + 1;
+            if (st && st->res_history && st->res_history_len < st->res_history_cap)
+                st->res_history[st->res_history_len++] = gabs / bnorm;
+            if (!std::isfinite(gabs) || !std::isfinite(hn)) {
+                broke = true;
+                break;
+            }
+            if (gabs <= tol * bnorm || hn == 0.0 || its >= h->o.max_iter) break;
+            launch_scale_dev(n, h->w, dsc + Dsc::HN, 1, h->V + (int64_t)(j + 1) * n, s);
+        }
+        if (broke) {
+            status = MGR_E_BREAKDOWN;
+            break;
+        }
+        launch_trisolve(k, m, dsc, s);
+        launch_zaxpy(n, k, h->Z, dsc + Dsc::y(0, m), x, s);
+    }
+    sync(h);
+    if (st) {
+        st->iterations = its;
+        st->rel_residual = rel;
+    }
+    return status;
+}
+
+void fill_stats(mgr_handle *h, mgr_stats *st) {
+    if (!st) return;
+    st->setup_ms = h->setup_ms;
+    int k = 0;
+    for (auto &lv : h->lev)
+        if (k < 64) {
+            st->level_n[k] = lv.A.nrows;
+            st->level_nnz[k] = lv.A.nnz;
+            k++;
+        }
+    for (auto &lv : h->amg)
+        if (k < 64) {
+            st->level_n[k] = lv.A.nrows;
+            st->level_nnz[k] = lv.A.nnz;
+            k++;
+        }
+    st->n_levels = k;
+}
+
+void destroy_impl(mgr_handle *h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (void *p : h->allocs)
+        if (p) (void)hipFree(p);
+    for (auto e : h->ev) (void)hipEventDestroy(e);
+    if (h->hsc) (void)hipHostFree(h->hsc);
+    if (h->herr) (void)hipHostFree(h->herr);
+    delete h;
+}
+
+int check_options(const mgr_options *o, std::string &why) {
+    if (o->precision != 0 && o->precision != 1) why = "precision must be 0 or 1";
+    else if (o->restart < 1 || o->restart > 64) why = "restart must be in [1, 64]";
+    else if (o->max_iter < 0) why = "max_iter must be >= 0";
+    else if (o->rp_type < 0 || o->rp_type > 2) why = "rp_type must be 0, 1 or 2";
+    else if (o->f_sweeps < 0 || o->f_sweeps > 8) why = "f_sweeps must be in [0, 8]";
+    else if (!(o->amg_theta >= 0.0 && o->amg_theta < 1.0)) why = "amg_theta must be in [0, 1)";
+    else if (o->amg_pre < 0 || o->amg_pre > 8 || o->amg_post < 0 || o->amg_post > 8) why = "amg_pre/post in [0, 8]";
+    else if (o->amg_max_levels < 1 || o->amg_max_levels > 32) why = "amg_max_levels must be in [1, 32]";
+    else if (o->amg_coarse_max < 1) why = "amg_coarse_max must be >= 1";
+    else if (o->dense_max < 1 || o->dense_max > 4096) why = "dense_max must be in [1, 4096]";
+    else return MGR_OK;
+    return MGR_E_INVALID;
+}
+
+int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_options *opts, mgr_handle **out) {
+    *out = nullptr;
+    std::string why;
+    if (!Ain || !labels || !opts) {
+        g_err = "null argument";
+        return MGR_E_INVALID;
+    }
+    if (Ain->n <= 0 || Ain->nnz < 0 || Ain->nnz > INT_MAX || Ain->n > INT_MAX / 4 || (bs != 1 && bs != 3) ||
+        Ain->n % bs != 0 || !Ain->row_ptr || (Ain->nnz > 0 && (!Ain->col_idx || !Ain->values))) {
+        g_err = "invalid matrix size, block size or pointer";
+        return MGR_E_INVALID;
+    }
+    if (check_options(opts, why) != MGR_OK) {
+        g_err = why;
+        return MGR_E_INVALID;
+    }
+    mgr_handle *h = new (std::nothrow) mgr_handle();
+    if (!h) {
+        g_err = "host allocation failed";
+        return MGR_E_OOM;
+    }
+    try {
+        auto t0 = std::chrono::steady_clock::now();
+        h->stream = (hipStream_t)opts->stream;
+        h->o = *opts;
+        h->n = Ain->n;
+        h->bs = bs;
+        h->ncell = Ain->n / bs;
+        h->m = opts->restart;
+        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&h->herr), 8 * sizeof(int), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&h->hsc), 8 * sizeof(double), hipHostMallocDefault));
+        h->derr = dalloc<int>(h, 8);
+        const int64_t n = Ain->n, nnz = Ain->nnz;
+        // pattern and labels
+        int32_t ends[2];
+        HIPCHK(hipMemcpyAsync(&ends[0], Ain->row_ptr, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(&ends[1], Ain->row_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        sync(h);
+        if (ends[0] != 0 || ends[1] != nnz) throw_err(h, MGR_E_INVALID, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+        reset_err(h);
+        launch_validate(n, nnz, Ain->row_ptr, Ain->col_idx, labels, h->derr, h->stream);
+        read_err(h);
+        if (h->herr[0]) throw_err(h, MGR_E_INVALID, "row pointers or column indices invalid (need sorted, unique, in range)");
+        if (h->herr[2]) throw_err(h, MGR_E_INVALID, "cf_labels outside [0, 31]");
+        h->L = h->herr[1];
+        // private copy of A
+        DCsr &A = h->Ain;
+        A.nrows = A.ncols = n;
+        A.nnz = nnz;
+        A.rp = dalloc<int32_t>(h, n + 1);
+        A.ci = dalloc<int32_t>(h, nnz);
+        A.v = dalloc<double>(h, nnz);
+        HIPCHK(hipMemcpyAsync(A.rp, Ain->row_ptr, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+        if (nnz > 0) {
+            HIPCHK(hipMemcpyAsync(A.ci, Ain->col_idx, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(hipMemcpyAsync(A.v, Ain->values, nnz * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        }
+        h->A0 = opts->transpose ? transpose(h, A, true) : A;
+        h->A0.lanes = choose_lanes(h->A0);
+        build_csell(h);
+        if (opts->global_relax && h->L > 0) {
+            h->binv = dalloc<double>(h, h->ncell * bs * bs);
+            reset_err(h);
+            launch_block_inverse(h->ncell, bs, h->A0.rp, h->A0.ci, h->A0.v, h->binv, h->derr, h->stream);
+            read_err(h);
+            if (h->herr[3] != INT_MAX)
+                throw_err(h, MGR_E_SINGULAR_BLOCK, "singular diagonal cell block at cell " + std::to_string(h->herr[3]));
+        }
+        DCsr Acur = h->A0;
+        int32_t *lab = dalloc<int32_t>(h, n);
+        int32_t *glob = dalloc<int32_t>(h, n);
+        HIPCHK(hipMemcpyAsync(lab, labels, n * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+        {
+            std::vector<int32_t> iota(n);
+            for (int64_t i = 0; i < n; ++i) iota[i] = (int32_t)i;
+            HIPCHK(hipMemcpyAsync(glob, iota.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+            sync(h);
+        }
+        h->lev.resize(h->L);
+        for (int l = 0; l < h->L; ++l) {
+            h->lev[l].A = Acur;
+            h->lev[l].lab = lab;
+            h->lev[l].glob = glob;
+            DCsr An;
+            build_mgr_level(h, l, An, lab, glob);
+            Acur = An;
+        }
+        build_amg(h, Acur);
+        for (auto &lv : h->lev) {
+            lv.A.lanes = choose_lanes(lv.A);
+            lv.P.lanes = choose_lanes(lv.P);
+            lv.R.lanes = choose_lanes(lv.R);
+        }
+        for (auto &lv : h->amg) {
+            lv.A.lanes = choose_lanes(lv.A);
+            lv.P.lanes = choose_lanes(lv.P);
+            lv.PT.lanes = choose_lanes(lv.PT);
+        }
+        if (h->o.precision == 1) to_mixed(h);
+        alloc_work(h);
+        const int m = h->m;
+        h->V = dalloc<double>(h, (int64_t)(m + 1) * n);
+        h->Z = dalloc<double>(h, (int64_t)m * n);
+        h->w = dalloc<double>(h, n);
+        h->res = dalloc<double>(h, n);
+        h->dsc = dalloc<double>(h, Dsc::size(m));
+        launch_fill_f64(h->dsc, 0.0, Dsc::size(m), h->stream);
+        h->part = dalloc<double>(h, (int64_t)kRedBlocks * 66);
+        sync(h);
+        h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = h;
+        return MGR_OK;
+    } catch (const Fail &f) {
+        destroy_impl(h);
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        destroy_impl(h);
+        g_err = "host allocation failed";
+        return MGR_E_OOM;
+    }
+}
+
+}  // namespace
+
+namespace mgr {
+int alloc(mgr_handle *h, void **p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return MGR_E_OOM;
+    }
+    h->allocs.push_back(*p);
+    return MGR_OK;
+}
+}  // namespace mgr
+
+extern "C" {
+
+void mgr_default_options(mgr_options *o) {
+    std::memset(o, 0, sizeof *o);
+    o->stream = nullptr;
+    o->precision = 0;
+    o->restart = 30;
+    o->max_iter = 400;
+    o->rp_type = 0;
+    o->global_relax = 1;
+    o->f_sweeps = 1;
+    o->amg_theta = 0.25;
+    o->amg_pre = 2;
+    o->amg_post = 2;
+    o->amg_max_levels = 25;
+    o->amg_coarse_max = 64;
+    o->dense_max = 4096;
+    o->pmis_seed = 0;
+    o->transpose = 0;
+    o->use_x0 = 0;
+}
+
+int mgr_setup(const mgr_csr *A, int block_size, const int32_t *cf_labels, const mgr_options *opts,
+              mgr_handle **out) {
+    if (!out) {
+        g_err = "null output handle pointer";
+        return MGR_E_INVALID;
+    }
+    return setup_impl(A, block_size, cf_labels, opts, out);
+}
+
+int mgr_solve(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) {
+    if (!h || !b || !x || !(tol >= 0.0)) {
+        g_err = "invalid solve arguments";
+        if (h) h->err = g_err;
+        return MGR_E_INVALID;
+    }
+    try {
+        auto t0 = std::chrono::steady_clock::now();
+        int rc = gmres(h, b, x, tol, st);
+        if (st) {
+            st->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            fill_stats(h, st);
+        }
+        if (rc == MGR_E_BREAKDOWN) h->err = "NaN or Inf in the right-hand side or the Krylov recurrence";
+        return rc;
+    } catch (const Fail &f) {
+        return f.code;
+    }
+}
+
+int mgr_pattern_outer(mgr_handle *h, const double *lambda, const double *x, double *dvals) {
+    if (!h || !lambda || !x || !dvals) return MGR_E_INVALID;
+    try {
+        launch_pattern_outer(h->Ain.nrows, h->Ain.rp, h->Ain.ci, lambda, x, dvals, h->stream);
+        HIPCHK(hipGetLastError());
+        return MGR_OK;
+    } catch (const Fail &f) {
+        return f.code;
+    }
+}
+
+int mgr_apply_preconditioner(mgr_handle *h, const double *r, double *z) {
+    if (!h || !r || !z) return MGR_E_INVALID;
+    try {
+        apply_prec(h, r, z);
+        sync(h);
+        return MGR_OK;
+    } catch (const Fail &f) {
+        return f.code;
+    }
+}
+
+int mgr_spmv(mgr_handle *h, const double *x, double *y) {
+    if (!h || !x || !y) return MGR_E_INVALID;
+    try {
+        fine_op<double>(h, 0, x, nullptr, y);
+        sync(h);
+        return MGR_OK;
+    } catch (const Fail &f) {
+        return f.code;
+    }
+}
+
+void mgr_destroy(mgr_handle *h) { destroy_impl(h); }
+
+const char *mgr_status_string(int code) {
+    switch (code) {
+    case MGR_OK: return "MGR_OK";
+    case MGR_NOT_CONVERGED: return "MGR_NOT_CONVERGED";
+    case MGR_E_INVALID: return "MGR_E_INVALID";
+    case MGR_E_ZERO_FDIAG: return "MGR_E_ZERO_FDIAG";
+    case MGR_E_SINGULAR_BLOCK: return "MGR_E_SINGULAR_BLOCK";
+    case MGR_E_BREAKDOWN: return "MGR_E_BREAKDOWN";
+    case MGR_E_HIP: return "MGR_E_HIP";
+    case MGR_E_OOM: return "MGR_E_OOM";
+    }
+    return "unknown status";
+}
+
+const char *mgr_last_error(const mgr_handle *h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+int mgr_num_levels(mgr_handle *h, int *nm, int *na) {
+    if (!h) return MGR_E_INVALID;
+    if (nm) *nm = h->L;
+    if (na) *na = (int)h->amg.size();
+    return MGR_OK;
+}
+
+int mgr_get_matrix(mgr_handle *h, int kind, int level, int64_t *nrows, int64_t *ncols, int64_t *nnz,
+                   int32_t *row_ptr, int32_t *col_idx, double *values) {
+    if (!h) return MGR_E_INVALID;
+    const DCsr *M = nullptr;
+    const int na = (int)h->amg.size();
+    if (kind >= 0 && kind <= 2) {
+        if (level < 0 || level >= h->L) return MGR_E_INVALID;
+        M = kind == 0 ? &h->lev[level].A : kind == 1 ? &h->lev[level].P : &h->lev[level].R;
+    } else if (kind == 3) {
+        if (level < 0 || level >= na) return MGR_E_INVALID;
+        M = &h->amg[level].A;
+    } else if (kind == 4 || kind == 5) {
+        if (level < 0 || level >= na - 1) return MGR_E_INVALID;
+        M = kind == 4 ? &h->amg[level].P : &h->amg[level].S;
+    } else {
+        return MGR_E_INVALID;
+    }
+    if (nrows) *nrows = M->nrows;
+    if (ncols) *ncols = M->ncols;
+    if (nnz) *nnz = M->nnz;
+    if (!row_ptr) return MGR_OK;
+    try {
+        sync(h);
+        HIPCHK(hipMemcpy(row_ptr, M->rp, (M->nrows + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (col_idx && M->nnz) HIPCHK(hipMemcpy(col_idx, M->ci, M->nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (values && M->v && M->nnz) HIPCHK(hipMemcpy(values, M->v, M->nnz * sizeof(double), hipMemcpyDeviceToHost));
+        return MGR_OK;
+    } catch (const Fail &f) {
+        return f.code;
+    }
+}
+
+int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len) {
+    if (!h || !len) return MGR_E_INVALID;
+    const int na = (int)h->amg.size();
+    const void *src = nullptr;
+    size_t esz = 8;
+    int64_t n = -1;
+    switch (kind) {
+    case 0: n = h->binv ? h->ncell * h->bs * h->bs : 0; src = h->binv; break;
+    case 1: if (level >= 0 && level < h->L) { n = h->lev[level].nF; src = h->lev[level].dinv; } break;
+    case 2: if (level >= 0 && level < h->L) { n = h->lev[level].nF; src = h->lev[level].flist; esz = 4; } break;
+    case 3: if (level >= 0 && level < h->L) { n = h->lev[level].nC; src = h->lev[level].clist; esz = 4; } break;
+    case 4: if (level >= 0 && level < na - 1) { n = h->amg[level].n; src = h->amg[level].cf; esz = 4; } break;
+    case 5: if (level >= 0 && level < na - 1) { n = h->amg[level].n; src = h->amg[level].l1; } break;
+    case 6: n = h->ncoarse * h->ncoarse; src = h->lu; break;
+    case 7: n = h->ncoarse; src = h->perm; esz = 4; break;
+    default: break;
+    }
+    if (n < 0) return MGR_E_INVALID;
+    *len = n;
+    if (!out || n == 0) return MGR_OK;
+    try {
+        sync(h);
+        if (kind == 0) {
+            // device planes -> row-major 3x3 (or 1x1) per cell
+            const int bb = h->bs * h->bs;
+            std::vector<double> planes(n);
+            HIPCHK(hipMemcpy(planes.data(), src, n * sizeof(double), hipMemcpyDeviceToHost));
+            double *o = static_cast<double *>(out);
+            for (int64_t c = 0; c < h->ncell; ++c)
+                for (int k = 0; k < bb; ++k) o[c * bb + k] = planes[(int64_t)k * h->ncell + c];
+        } else {
+            HIPCHK(hipMemcpy(out, src, n * esz, hipMemcpyDeviceToHost));
+        }
+        return MGR_OK;
+    } catch (const Fail &f) {
+        return f.code;
+    }
+}
+
+int mgr_set_kernel_timing(mgr_handle *h, int on) {
+    if (!h) return MGR_E_INVALID;
+    h->timing = on != 0;
+    h->ev_used = 0;
+    h->t_bytes = 0;
+    h->t_launches = 0;
+    return MGR_OK;
+}
+
+int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launches, double *bytes_total) {
+    if (!h || kernel != 0) return MGR_E_INVALID;
+    try {
+        sync(h);
+        double tot = 0.0;
+        for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
+            tot += ms;
+        }
+        if (total_ms) *total_ms = tot;
+        if (launches) *launches = h->t_launches;
+        if (bytes_total) *bytes_total = h->t_bytes;
+        h->ev_used = 0;
+        h->t_bytes = 0;
+        h->t_launches = 0;
+        return MGR_OK;
+    } catch (const Fail &f) {
+        return f.code;
+    }
+}
+
+}  // extern "C"

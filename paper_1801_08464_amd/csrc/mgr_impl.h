@@ -1,0 +1,239 @@
+// Internal declarations of libmgr (HIP, gfx950).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mgr.h"
+
+namespace mgr {
+
+constexpr int kWave = 64;
+
+// Device CSR (int32 row pointers and columns).  vf is the FP32 copy of the
+// values used by the mixed-precision hierarchy.
+struct DCsr {
+    int64_t nrows = 0, ncols = 0, nnz = 0;
+    int32_t *rp = nullptr, *ci = nullptr;
+    double *v = nullptr;
+    float *vf = nullptr;
+    int lanes = 1;  // threads per row of the vector SpMV kernel
+};
+
+// Cell-sliced ELL of the level-0 operator: 64 consecutive cells form a slice;
+// inside a slice, the rows of component v (u = bs*c + v) form one ELL block of
+// width w[s*bs+v] stored slot-major (slot t of lane l at (off + t)*64 + l), so
+// every load of a wavefront is one contiguous 256/512-byte segment and only the
+// matrix's true nonzeros (plus per-slice padding) are stored.
+struct CSell {
+    int64_t ncell = 0, nslice = 0, nslot = 0, nnz_true = 0;
+    int bs = 1;
+    int32_t *off = nullptr;    // nslice*bs: first slot group of (slice, component)
+    int32_t *width = nullptr;  // nslice*bs
+    int32_t *col = nullptr;    // nslot*64 (-1 = padding)
+    double *v = nullptr;
+    float *vf = nullptr;
+};
+
+struct MgrLevel {
+    int64_t n = 0, nF = 0, nC = 0;
+    DCsr A, P, R;
+    int32_t *flist = nullptr, *clist = nullptr, *fmap = nullptr;
+    int32_t *lab = nullptr, *glob = nullptr;
+    double *dinv = nullptr;
+    float *dinvf = nullptr;
+    bool aff_diag = false;  // A_FF diagonal: the F-relaxation may update in place
+    // V-cycle work vectors
+    double *e = nullptr, *t = nullptr, *r = nullptr;
+    float *ef = nullptr, *tf = nullptr, *rf = nullptr;
+};
+
+struct AmgLevel {
+    int64_t n = 0, nc = 0;
+    DCsr A, P, PT, S;
+    int32_t *cf = nullptr;
+    double *l1 = nullptr;
+    float *l1f = nullptr;
+    double *r = nullptr, *x = nullptr, *x2 = nullptr, *t = nullptr;
+    float *rf = nullptr, *xf = nullptr, *x2f = nullptr, *tf = nullptr;
+};
+
+}  // namespace mgr
+
+struct mgr_handle {
+    hipStream_t stream = nullptr;
+    mgr_options o{};
+    int64_t n = 0, ncell = 0;
+    int bs = 1, L = 0;
+    std::string err;
+    std::vector<void *> allocs;
+
+    mgr::DCsr Ain;   // the matrix as passed (pattern of mgr_pattern_outer)
+    mgr::DCsr A0;    // level-0 operator (A or A^T)
+    mgr::CSell A0s;  // its sliced form
+    double *binv = nullptr;  // 9 planes of ncell (bs = 3) or 1 plane (bs = 1)
+    float *binvf = nullptr;
+    std::vector<mgr::MgrLevel> lev;
+    std::vector<mgr::AmgLevel> amg;
+    int64_t ncoarse = 0;
+    double *lu = nullptr;
+    int32_t *perm = nullptr;
+    double *lu_b = nullptr, *lu_x = nullptr;
+
+    // Krylov workspace
+    int m = 30;
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *res = nullptr;
+    double *dsc = nullptr;   // device scalars and Hessenberg storage
+    double *part = nullptr;  // per-block partial sums
+    int nblk_red = 0;
+    double *hsc = nullptr;   // pinned host mirror of a few scalars
+    int *derr = nullptr;     // device error words
+    int *herr = nullptr;     // pinned host copy
+
+    // timing of the fine-level kernel
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    double t_bytes = 0;
+    int64_t t_launches = 0;
+    double setup_ms = 0;
+};
+
+namespace mgr {
+
+// ---- helpers (mgr_host.cpp) ----
+int alloc(mgr_handle *h, void **p, size_t bytes);
+template <typename T>
+inline int alloc_n(mgr_handle *h, T **p, int64_t n) {
+    return alloc(h, reinterpret_cast<void **>(p), (size_t)(n > 0 ? n : 1) * sizeof(T));
+}
+inline unsigned nblocks(int64_t n, int bt) { return (unsigned)((n + bt - 1) / bt); }
+
+// ---- utility kernels (k_util.hip) ----
+void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
+void launch_cast_f64_f32(const double *a, float *b, int64_t n, hipStream_t s);
+void launch_cast_f32_f64(const float *a, double *b, int64_t n, hipStream_t s);
+// out[0..n] = exclusive scan of in[0..n-1], out[n] = total.  tmp: >= scan_tmp_words(n) int64.
+int64_t scan_tmp_words(int64_t n);
+void launch_scan(const int32_t *in, int32_t *out, int64_t n, int64_t *tmp, hipStream_t s);
+
+// ---- setup kernels (k_setup.hip) ----
+void launch_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const int32_t *lab, int *err,
+                     hipStream_t s);
+void launch_csell_count(int64_t ncell, int bs, const int32_t *rp, int32_t *rowlen, hipStream_t s);
+void launch_csell_width(int64_t nslice, int bs, int64_t ncell, const int32_t *rowlen, int32_t *width,
+                        hipStream_t s);
+void launch_csell_fill(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v,
+                       const int32_t *off, const int32_t *width, int32_t *col, double *val, hipStream_t s);
+void launch_block_inverse(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v, double *binv,
+                          int *err, hipStream_t s);
+void launch_level_flags(int64_t n, const int32_t *lab, int l, int32_t *isF, int32_t *isC, hipStream_t s);
+void launch_level_maps(int64_t n, const int32_t *lab, int l, const int32_t *fpos, const int32_t *cpos, int32_t *fmap,
+                       int32_t *cmap, int32_t *flist, int32_t *clist, hipStream_t s);
+void launch_fdiag_inverse(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
+                          double *dinv, int *err, int *offdiag_flag, const int32_t *fmap, hipStream_t s);
+void launch_p_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cmap, int rp_type, int32_t *cnt,
+                    hipStream_t s);
+void launch_p_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *cmap,
+                   const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Prp, int32_t *Pci, double *Pv,
+                   hipStream_t s);
+void launch_r_count(int64_t nC, const int32_t *clist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
+                    int rp_type, int32_t *cnt, hipStream_t s);
+void launch_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, const int32_t *ci, const double *v,
+                   const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Rrp, int32_t *Rci,
+                   double *Rv, hipStream_t s);
+void launch_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst, hipStream_t s);
+// SpGEMM C = A B, canonical ascending-k summation.  pass 0 counts into cnt, pass 1 fills.
+int spgemm_max_row();
+void launch_spgemm(int pass, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,
+                   const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci, double *Cv, int *err,
+                   hipStream_t s);
+// stable transpose: count (atomics), fill (atomics), then per-row sort by source row
+void launch_transpose_count(int64_t nrows, const int32_t *rp, const int32_t *ci, int32_t *cnt, hipStream_t s);
+void launch_transpose_fill(int64_t nrows, const int32_t *rp, const int32_t *ci, const double *v, int32_t *next,
+                           int32_t *Tci, double *Tv, hipStream_t s);
+void launch_transpose_sort(int64_t ncols, const int32_t *Trp, int32_t *Tci, double *Tv, hipStream_t s);
+// classical AMG
+void launch_strength(int pass, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
+                     int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag, hipStream_t s);
+void launch_pmis_init(int64_t n, const int32_t *STrp, int32_t *state, hipStream_t s);
+void launch_pmis_select(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *STrp, const int32_t *STci,
+                        const int32_t *state, uint64_t seed, int32_t *newc, hipStream_t s);
+void launch_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *newc, int32_t *state,
+                        int *counters, hipStream_t s);
+void launch_cf_flags(int64_t n, const int32_t *state, int32_t *isC, hipStream_t s);
+void launch_interp_count(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *sflag, const int32_t *cf,
+                         int32_t *cnt, hipStream_t s);
+void launch_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *sflag,
+                        const int32_t *cf, const int32_t *cmap, const int32_t *Prp, int32_t *Pci, double *Pv,
+                        hipStream_t s);
+void launch_l1(int64_t n, const int32_t *rp, const double *v, double *l1, int *err, hipStream_t s);
+void launch_dense_lu(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *lu, int32_t *perm,
+                     int *err, hipStream_t s);
+void launch_pattern_outer(int64_t n, const int32_t *rp, const int32_t *ci, const double *lam, const double *x,
+                          double *d, hipStream_t s);
+
+// ---- solve-phase kernels (k_solve.hip) ----
+template <typename T>
+void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s);
+// mode 0: y = A x;  1: y = r - A x;  2: y += A x;  3: y = x + (r - A x) / d (x != y)
+template <typename T>
+void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s);
+// F-row residual t[f] = r[i] - (A e)[i], i = flist[f]
+template <typename T>
+void launch_csr_rows_residual(const DCsr &A, const T *vals, int64_t nrows, const int32_t *rows, const T *e,
+                              const T *r, T *t, hipStream_t s);
+template <typename T>
+void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, hipStream_t s);
+template <typename T>
+void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T *r, T *e, hipStream_t s);
+template <typename T>
+void launch_frelax_scatter(int64_t nF, const int32_t *flist, const T *dinv, const T *t, T *e, hipStream_t s);
+template <typename T>
+void launch_frelax_inplace(const DCsr &A, const T *vals, int64_t nF, const int32_t *flist, const T *dinv,
+                           const T *r, T *e, hipStream_t s);
+template <typename T>
+void launch_div(int64_t n, const T *r, const T *d, T *x, hipStream_t s);
+template <typename T>
+void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s);
+
+// ---- Krylov kernels (k_krylov.hip) ----
+constexpr int kRedBlocks = 1024;
+int red_blocks(int64_t n);  // number of partial sums the reduction kernels write
+// partial sums over blocks of <w, V_i> (i < nv) and <w, w>: part[b*(nv+1) + i]
+void launch_mdot(int64_t n, int nv, const double *V, const double *w, double *part, const int *guard,
+                 hipStream_t s);
+// w -= sum_i h[i] V_i and partial <w,w>: part[b]
+void launch_maxpy_norm(int64_t n, int nv, const double *V, const double *h, double *w, double *part,
+                       const int *guard, hipStream_t s);
+// x += sum_i y[i] Z_i
+void launch_zaxpy(int64_t n, int nv, const double *Z, const double *y, double *x, hipStream_t s);
+void launch_norm_part(int64_t n, const double *a, double *part, hipStream_t s);
+// y = a * scal[0]  (scal device), or y = a / scal[0] when divide
+void launch_scale_dev(int64_t n, const double *a, const double *scal, int divide, double *y, hipStream_t s);
+void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
+// single-block finishers operating on the device scalar block
+void launch_arnoldi_fin(int stage, int j, int m, int nblk, const double *part, double *dsc, int *guard,
+                        hipStream_t s);
+void launch_givens(int j, int m, double *dsc, hipStream_t s);
+void launch_trisolve(int k, int m, double *dsc, hipStream_t s);
+void launch_norm_fin(int nblk, const double *part, double *out, hipStream_t s);
+
+// layout of the device scalar block dsc (doubles)
+struct Dsc {
+    __host__ __device__ static int H(int i, int j, int m) { return 64 + i * m + j; }  // (m+1) x m Hessenberg
+    __host__ __device__ static int g(int i, int m) { return 64 + (m + 1) * m + i; }  // m+1
+    __host__ __device__ static int cs(int i, int m) { return 64 + (m + 1) * m + (m + 1) + i; }
+    __host__ __device__ static int sn(int i, int m) { return 64 + (m + 1) * m + (m + 1) + m + i; }
+    __host__ __device__ static int y(int i, int m) { return 64 + (m + 1) * m + (m + 1) + 2 * m + i; }
+    __host__ __device__ static int hcur(int i, int m) { return 64 + (m + 1) * m + (m + 1) + 3 * m + i; }
+    __host__ __device__ static int size(int m) { return 64 + (m + 1) * m + (m + 1) + 4 * m + 1 + 8; }
+    // scalar slots
+    enum { BNORM = 0, WN0 = 1, WN = 2, GABS = 3, HN = 4, INVH = 5, BETA = 6, RNORM = 7 };
+};
+
+}  // namespace mgr

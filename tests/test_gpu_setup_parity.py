@@ -1,0 +1,111 @@
+"""Setup parity: every hierarchy object built on the GPU is bit-for-bit equal to
+the oracle's (C/F splits, patterns and values), on seeded systems that span
+several 64-cell slices with a ragged last slice."""
+import numpy as np
+import pytest
+
+from gpu_common import assert_same_csr, gpu_solver, oracle_csr, small_system
+from synth import make_config, make_poisson
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "cfg1_32x32": lambda: make_config(1),
+    "2d_37x29_band": lambda: small_system((37, 29), seed=8, sigma=2.0, frac=0.3, region="band"),
+    "3d_13x11x9_ball": lambda: small_system((13, 11, 9), seed=4, sigma=2.0, frac=0.3, region="ball"),
+}
+
+
+def compare_hierarchy(orc, s, **opts):
+    o = orc.Oracle(oracle_csr(orc, s), s.labels, **opts)
+    g = gpu_solver(s, **{k: v for k, v in opts.items() if k != "precision"})
+    try:
+        nm, na = g.levels
+        assert (nm, na) == (o.n_mgr_levels, o.n_amg_levels)
+        if o.n_mgr_levels > 0 and opts.get("global_relax", 1):
+            np.testing.assert_array_equal(g.get_vector(0), o.block_inverses(), err_msg="cell-block inverses")
+        for l in range(nm):
+            ol = o.mgr_level(l)
+            assert_same_csr(g.get_matrix(0, l), ol["A"], f"MGR A_{l}")
+            assert_same_csr(g.get_matrix(1, l), ol["P"], f"MGR P_{l}")
+            assert_same_csr(g.get_matrix(2, l), ol["R"], f"MGR R_{l}")
+            np.testing.assert_array_equal(g.get_vector(1, l), ol["dinv"], err_msg=f"dinv_{l}")
+            np.testing.assert_array_equal(g.get_vector(2, l), ol["flist"], err_msg=f"F list {l}")
+            np.testing.assert_array_equal(g.get_vector(3, l), ol["clist"], err_msg=f"C list {l}")
+        for k in range(na):
+            ok = o.amg_level(k)
+            assert_same_csr(g.get_matrix(3, k), ok["A"], f"AMG A_{k}")
+            if k < na - 1:
+                np.testing.assert_array_equal(g.get_vector(4, k), ok["cf"], err_msg=f"AMG C/F split {k}")
+                assert_same_csr(g.get_matrix(5, k), ok["S"], f"AMG strength {k}")
+                assert_same_csr(g.get_matrix(4, k), ok["P"], f"AMG P_{k}")
+                np.testing.assert_array_equal(g.get_vector(5, k), ok["l1"], err_msg=f"AMG l1 {k}")
+        lu, perm = o.coarse_lu()
+        np.testing.assert_array_equal(g.get_vector(7), perm, err_msg="coarsest LU permutation")
+        np.testing.assert_array_equal(g.get_vector(6), lu.ravel(), err_msg="coarsest LU factors")
+    finally:
+        g.close()
+        o.close()
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_hierarchy_bitwise(orc, case):
+    s = CASES[case]()
+    print(f"[setup parity] {case} n={s.n} nnz={s.nnz}", flush=True)
+    compare_hierarchy(orc, s)
+
+
+@pytest.mark.parametrize("opts", [dict(rp_type=1), dict(rp_type=2), dict(global_relax=0),
+                                  dict(amg_theta=0.5, pmis_seed=12345), dict(amg_coarse_max=10)])
+def test_hierarchy_bitwise_options(orc, opts):
+    s = small_system((19, 17), seed=6)
+    print(f"[setup parity] options {opts}", flush=True)
+    compare_hierarchy(orc, s, **opts)
+
+
+def test_hierarchy_bitwise_transpose(orc):
+    s = small_system((23, 21), seed=2)
+    At = orc.transpose(oracle_csr(orc, s))
+    o = orc.Oracle(At, s.labels)
+    g = gpu_solver(s, transpose=True)
+    try:
+        for l in range(o.n_mgr_levels):
+            assert_same_csr(g.get_matrix(0, l), o.mgr_level(l)["A"], f"A^T hierarchy level {l}")
+        for k in range(o.n_amg_levels):
+            assert_same_csr(g.get_matrix(3, k), o.amg_level(k)["A"], f"A^T AMG level {k}")
+    finally:
+        g.close()
+
+
+def test_plain_amg_poisson_bitwise(orc):
+    ip, ix, dv, _ = make_poisson((45, 39))
+    n = ip.shape[0] - 1
+
+    class S:  # minimal system record
+        pass
+    s = S()
+    s.indptr, s.indices, s.data, s.labels = ip, ix, dv, np.zeros(n, np.int32)
+    o = orc.Oracle(orc.as_csr(ip, ix, dv), s.labels, block_size=1)
+    g = gpu_solver(s, block_size=1)
+    try:
+        assert g.levels == (0, o.n_amg_levels)
+        for k in range(o.n_amg_levels):
+            assert_same_csr(g.get_matrix(3, k), o.amg_level(k)["A"], f"AMG A_{k}")
+            if k < o.n_amg_levels - 1:
+                np.testing.assert_array_equal(g.get_vector(4, k), o.amg_level(k)["cf"])
+                assert_same_csr(g.get_matrix(4, k), o.amg_level(k)["P"], f"AMG P_{k}")
+    finally:
+        g.close()
+
+
+def test_setup_is_deterministic(orc):
+    s = small_system((21, 20, 3), seed=9)
+    a, b = gpu_solver(s), gpu_solver(s)
+    try:
+        for k in range(a.levels[1]):
+            ma, mb = a.get_matrix(3, k), b.get_matrix(3, k)
+            for x, y in zip(ma[:3], mb[:3]):
+                np.testing.assert_array_equal(x, y)
+    finally:
+        a.close()
+        b.close()

@@ -1,0 +1,164 @@
+"""Solve-phase parity of the HIP path against the oracle: the fine SpMV, one
+V-cycle, full MGR-GMRES (iteration count within 1, matched-iteration solution
+error), the mixed-precision form, status codes and edge cases."""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_solver, oracle_csr, small_system
+from synth import make_config, make_poisson, random_vector
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fine_spmv_bitwise(orc):
+    for s in (make_config(1), small_system((13, 11, 9), seed=4, sigma=2.0, frac=0.3, region="ball")):
+        print(f"[spmv] n={s.n}", flush=True)
+        A = oracle_csr(orc, s)
+        g = gpu_solver(s)
+        x = random_vector(s.n, 5)
+        y = g.spmv(x).cpu().numpy()
+        np.testing.assert_array_equal(y, orc.spmv(A, x))
+        g.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_vcycle_matches_oracle(orc, precision):
+    s = small_system((29, 23), seed=12, sigma=2.0, frac=0.35)
+    o = orc.Oracle(oracle_csr(orc, s), s.labels, precision=1 if precision == "mixed" else 0)
+    g = gpu_solver(s, precision=precision)
+    r = random_vector(s.n, 1)
+    z = g.apply_preconditioner(r).cpu().numpy()
+    ze = o.vcycle(r)
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    assert np.linalg.norm(z - ze) / np.linalg.norm(ze) < tol
+    g.close()
+
+
+@pytest.mark.parametrize("cfg", [1, "3d"])
+def test_solve_matches_oracle(orc, cfg):
+    s = make_config(1) if cfg == 1 else small_system((24, 24, 24), seed=3, sigma=1.5, frac=0.35, region="ball")
+    print(f"[solve] cfg={cfg} n={s.n}", flush=True)
+    A = oracle_csr(orc, s)
+    ro = orc.Oracle(A, s.labels).solve(s.b, 1e-8)
+    assert ro.status == 0
+    g = gpu_solver(s)
+    x, info = g.solve(s.b, 1e-8)
+    x = x.cpu().numpy()
+    assert info.status == 0
+    assert abs(info.iterations - ro.iterations) <= 1, (info.iterations, ro.iterations)
+    res = np.linalg.norm(s.b - orc.spmv(A, x)) / np.linalg.norm(s.b)
+    assert res <= 1e-8 and info.rel_residual <= 1e-8
+    assert info.level_n == ro.level_n and info.level_nnz == ro.level_nnz
+    g.close()
+    # matched-iteration mode: the same number of Arnoldi steps with tol = 0
+    gm = gpu_solver(s, max_iter=ro.iterations)
+    xm, im = gm.solve(s.b, 0.0)
+    assert im.iterations == ro.iterations
+    err = np.linalg.norm(xm.cpu().numpy() - ro.x) / np.linalg.norm(ro.x)
+    assert err <= 1e-8, err
+    gm.close()
+
+
+@pytest.mark.parametrize("cfg", [1, "3d"])
+def test_mixed_precision_solve(orc, cfg):
+    s = make_config(1) if cfg == 1 else small_system((24, 24, 24), seed=3, sigma=1.5, frac=0.35, region="ball")
+    A = oracle_csr(orc, s)
+    ro = orc.Oracle(A, s.labels, precision=1).solve(s.b, 1e-8)
+    g = gpu_solver(s, precision="mixed")
+    x, info = g.solve(s.b, 1e-8)
+    assert info.status == 0
+    assert abs(info.iterations - ro.iterations) <= 1, (info.iterations, ro.iterations)
+    res = np.linalg.norm(s.b - orc.spmv(A, x.cpu().numpy())) / np.linalg.norm(s.b)
+    assert res <= 1e-8
+    g.close()
+
+
+def test_residual_history_monotone():
+    s = small_system((32, 32), seed=4, sigma=2.0)
+    g = gpu_solver(s, restart=5)
+    x, info = g.solve(s.b, 1e-10)
+    h = info.history
+    assert info.status == 0 and len(h) == info.iterations
+    assert np.all(h[1:] <= h[:-1] * (1 + 1e-6))
+    g.close()
+
+
+@pytest.mark.parametrize("opts", [dict(rp_type=1), dict(rp_type=2), dict(global_relax=0), dict(f_sweeps=0),
+                                  dict(f_sweeps=2), dict(amg_pre=1, amg_post=3), dict(amg_pre=0, amg_post=1),
+                                  dict(restart=1, max_iter=2000), dict(restart=64)])
+def test_option_variants_match_oracle(orc, opts):
+    s = small_system((19, 17), seed=6)
+    A = oracle_csr(orc, s)
+    ro = orc.Oracle(A, s.labels, **opts).solve(s.b, 1e-8)
+    g = gpu_solver(s, **opts)
+    x, info = g.solve(s.b, 1e-8)
+    assert info.status == ro.status
+    if ro.status == 0:
+        assert abs(info.iterations - ro.iterations) <= 1, (opts, info.iterations, ro.iterations)
+    g.close()
+
+
+def test_plain_amg_and_block_size_one(orc):
+    ip, ix, dv, b = make_poisson((40, 33))
+    n = ip.shape[0] - 1
+    from paper_1801_08464_amd.solver import MGRSolver
+    ro = orc.Oracle(orc.as_csr(ip, ix, dv), np.zeros(n, np.int32), block_size=1).solve(b, 1e-8)
+    g = MGRSolver(ip, ix, dv, np.zeros(n, np.int32), block_size=1)
+    x, info = g.solve(b, 1e-8)
+    assert info.status == 0 and abs(info.iterations - ro.iterations) <= 1
+    g.close()
+
+
+def test_tiny_systems(orc):
+    # one cell (coarse grid of one unknown), and a grid whose whole hierarchy is a dense LU
+    for grid in ((1, 1), (2, 1), (3, 3)):
+        s = small_system(grid, seed=1, frac=0.5)
+        A = oracle_csr(orc, s)
+        ro = orc.Oracle(A, s.labels).solve(s.b, 1e-10)
+        g = gpu_solver(s)
+        x, info = g.solve(s.b, 1e-10)
+        assert info.status == 0 and abs(info.iterations - ro.iterations) <= 1
+        np.testing.assert_allclose(x.cpu().numpy(), s.x_true, rtol=1e-7, atol=1e-7)
+        g.close()
+
+
+def test_zero_rhs_and_initial_guess():
+    s = small_system()
+    g = gpu_solver(s, use_x0=1)
+    x, info = g.solve(np.zeros(s.n), 1e-8, x0=np.ones(s.n))
+    assert info.status == 0 and info.iterations == 0 and not x.cpu().numpy().any()
+    x, info = g.solve(s.b, 1e-8, x0=s.x_true)
+    assert info.status == 0 and info.iterations == 0
+    g.close()
+
+
+def test_status_codes_through_the_abi():
+    from paper_1801_08464_amd import binding as B
+    s = small_system()
+    bad = s.labels.copy()
+    two = np.where(s.two_phase)[0][0]
+    bad[3 * two + 2] = 0
+    with pytest.raises(B.MGRError) as e:
+        gpu_solver(s.__class__(**{**s.__dict__, "labels": bad}))
+    assert e.value.code == B.E_ZERO_FDIAG and str(3 * two + 2) in str(e.value)
+    with pytest.raises(B.MGRError) as e:
+        gpu_solver(s.__class__(**{**s.__dict__, "labels": np.full(s.n, 40, np.int32)}))
+    assert e.value.code == B.E_INVALID
+    unsorted = s.indices.copy()
+    unsorted[[0, 1]] = unsorted[[1, 0]]
+    with pytest.raises(B.MGRError) as e:
+        gpu_solver(s.__class__(**{**s.__dict__, "indices": unsorted}))
+    assert e.value.code == B.E_INVALID
+    with pytest.raises(B.MGRError) as e:
+        gpu_solver(s, restart=0)
+    assert e.value.code == B.E_INVALID
+    g = gpu_solver(s, max_iter=1)
+    x, info = g.solve(s.b, 1e-12)
+    assert info.status == B.NOT_CONVERGED and info.iterations == 1 and np.isfinite(x.cpu().numpy()).all()
+    g.close()
+    g = gpu_solver(s)
+    b = s.b.copy()
+    b[3] = np.nan
+    x, info = g.solve(b, 1e-8)
+    assert info.status == B.E_BREAKDOWN
+    g.close()
