@@ -1,0 +1,223 @@
+"""Benchmark: MGR-GMRES unknowns/s to a 1e-8 relative residual on one MI355X.
+
+Workload (default): the 3D 128^3 NCP-shaped Jacobian (6,291,456 unknowns,
+permeability contrast sigma = 2.0, 30 % two-phase cells in a seeded ball),
+restart 30, tolerance 1e-8.  One step = one whole job from the CSR matrix
+resident in HBM: mgr_setup (hierarchy built on the GPU) + mgr_solve.  The
+FP64 form gives `value`; the mixed-precision form (FP32 hierarchy inside FP64
+flexible GMRES) and the adjoint form (hierarchy on A^T + adjoint solve +
+pattern scatter) are timed the same way and reported beside it.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MGR-GMRES unknowns/s to 1e-8 rel. residual, FP64 vs mixed; V-cycle % HBM peak"
+HBM_PEAK_GBS = 8000.0
+# The paper's setup for its phase-transition runs (Section 6.2): non-injective R/P
+# (eq. non_injective_rp) at every reduction, Jacobi F-relaxation at the first
+# reduction, one AMG V(1,1)-cycle on A_FF at the second, AMG V(2,2) on the coarse
+# grid.  The last (constraint) reduction keeps Jacobi: its F-block has no strong
+# couplings for AMG to coarsen.
+SOLVER_OPTS = dict(frelax_amg_mask=2, frelax_amg_pre=1, frelax_amg_post=1)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_form(s, dev, form, steps, warmup, tol, timing=False):
+    import numpy as np
+    import torch
+
+    from paper_1801_08464_amd.solver import MGRSolver
+
+    rp = torch.as_tensor(s.indptr, device=dev)
+    ci = torch.as_tensor(s.indices, device=dev)
+    vals = torch.as_tensor(s.data, device=dev)
+    lab = torch.as_tensor(s.labels, device=dev)
+    if form == "adjoint":
+        # dL/dx of L = sum of p over the observation cells
+        g = np.zeros(s.n)
+        g[3 * s.obs_cells] = 1.0
+        rhs = torch.as_tensor(g, device=dev)
+    else:
+        rhs = torch.as_tensor(s.b, device=dev)
+    kw = dict(precision="mixed" if form == "mixed" else "fp64", transpose=(form == "adjoint"), **SOLVER_OPTS)
+    fwd_x = None
+    if form == "adjoint":
+        f = MGRSolver(rp, ci, vals, lab, **kw | dict(transpose=False))
+        fwd_x, _ = f.solve(torch.as_tensor(s.b, device=dev), tol)
+        f.close()
+
+    def one_step(keep, timed):
+        g = MGRSolver(rp, ci, vals, lab, **kw)
+        if timed and timing:
+            g.set_kernel_timing(True)
+        x, info = g.solve(rhs, tol)
+        if form == "adjoint":
+            d = g.pattern_outer(x, fwd_x)
+            keep.append(d)
+        keep.append(g)
+        return x, info
+
+    for w in range(warmup):
+        keep = []
+        one_step(keep, False)
+        torch.cuda.synchronize()
+        for k in keep:
+            if hasattr(k, "close"):
+                k.close()
+        log(f"{form}: warmup {w + 1}/{warmup} done")
+    keep, infos = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        x, info = one_step(keep, True)
+        infos.append(info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ktime = [k.kernel_time() for k in keep if hasattr(k, "kernel_time")] if timing else []
+    err = None
+    if form != "adjoint":
+        xt = torch.as_tensor(s.x_true, device=dev)
+        err = float(torch.linalg.norm(x - xt) / torch.linalg.norm(xt))
+    for k in keep:
+        if hasattr(k, "close"):
+            k.close()
+    del keep
+    torch.cuda.empty_cache()
+    info = infos[-1]
+    log(f"{form}: {steps} steps in {dt:.3f}s, iterations {info.iterations}, rel_res {info.rel_residual:.2e}")
+    out = dict(
+        ms_per_step=1e3 * dt / steps,
+        unknowns_per_s=s.n * steps / dt,
+        setup_ms=info.setup_ms,
+        solve_ms=info.solve_ms,
+        solve_unknowns_per_s=s.n / (info.solve_ms * 1e-3),
+        iterations=info.iterations,
+        rel_residual=info.rel_residual,
+        status=info.status,
+        levels=info.level_n,
+        level_nnz=info.level_nnz,
+    )
+    if err is not None:
+        out["rel_error_vs_x_true"] = err
+    if ktime:
+        ms = sum(k[0] for k in ktime)
+        cnt = sum(k[1] for k in ktime)
+        byt = sum(k[2] for k in ktime)
+        out["fine_kernel"] = dict(total_ms=ms, launches=cnt, avg_us=1e3 * ms / max(cnt, 1),
+                                  algorithmic_bytes=byt, achieved_GBs=byt / (ms * 1e-3) / 1e9 if ms > 0 else 0)
+    return out
+
+
+def cpu_baseline(cfg):
+    """The oracle (plain C, one thread) on one eighth of the workload: the same
+    generator and parameters at 64^3 cells."""
+    from oracle import oracle as O
+    from synth import CONFIGS, make_system
+    p = CONFIGS[cfg]
+    grid = tuple(g // 2 for g in p["grid"])
+    s = make_system(grid, p["sigma"], p["region"], p["frac"], p["seed"])
+    A = O.as_csr(s.indptr, s.indices, s.data)
+    t0 = time.perf_counter()
+    o = O.Oracle(A, s.labels, **SOLVER_OPTS)
+    r = o.solve(s.b, 1e-8)
+    dt = time.perf_counter() - t0
+    o.close()
+    return dict(value=s.n / dt, unit="unknowns/s", cores=1, kind="oracle",
+                sample=f"oracle setup+solve (FP64, 1 thread) on the same generator at {'x'.join(map(str, grid))} "
+                       f"({s.n} unknowns, 1/8 of the cells), {r.iterations} iterations, {dt:.1f} s",
+                cpu=platform.processor() or platform.machine())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--forms", default="fp64,mixed,adjoint")
+    ap.add_argument("--adjoint-config", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch of the fine kernel")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from synth import CONFIGS, make_config
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    s = make_config(args.config)
+    log(f"config {args.config}: n={s.n} nnz={s.nnz} generated in {time.perf_counter() - t:.1f}s")
+    forms = {}
+    for form in args.forms.split(","):
+        if form == "adjoint":
+            # the differentiable solve is specified on its own workload (48^3, 64 observation cells)
+            s5 = make_config(args.adjoint_config)
+            forms[form] = run_form(s5, dev, form, args.steps, args.warmup, args.tol)
+            forms[form]["workload"] = f"config {args.adjoint_config}: {'x'.join(map(str, CONFIGS[args.adjoint_config]['grid']))} " \
+                                      f"cells ({s5.n} unknowns); loss = sum of p over {len(s5.obs_cells)} cells; step = " \
+                                      "setup on A^T + adjoint solve + pattern scatter"
+            del s5
+        else:
+            forms[form] = run_form(s, dev, form, args.steps, args.warmup, args.tol, timing=(form == "fp64"))
+    main_form = forms.get("fp64") or next(iter(forms.values()))
+    p = CONFIGS[args.config]
+    fk = main_form.get("fine_kernel")
+    roof = None
+    if fk:
+        traffic = None
+        if args.traffic and os.path.exists(args.traffic):
+            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        roof = dict(bound="hbm", achieved=fk["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=fk["achieved_GBs"] / HBM_PEAK_GBS, traffic=traffic,
+                    kernel="k_csell (level-0 sliced-ELL SpMV / residual, FP64)",
+                    avg_us=fk["avg_us"], launches=fk["launches"],
+                    algorithmic_bytes_per_launch=fk["algorithmic_bytes"] / max(fk["launches"], 1))
+    line = {
+        "metric": METRIC,
+        "value": main_form["unknowns_per_s"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_form["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"config {args.config}: {'x'.join(map(str, p['grid']))} cells, 3 unknowns per cell "
+                               f"({s.n} unknowns, {s.nnz} nonzeros), sigma {p['sigma']}, two-phase {p['frac']:.0%} "
+                               f"{p['region']}; step = mgr_setup + mgr_solve to {args.tol:g}",
+                   "restart": 30, "tol": args.tol, "seed": p["seed"]},
+        "roofline": roof,
+        "forms": forms,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(args.config)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

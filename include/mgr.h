@@ -77,6 +77,10 @@ typedef struct {
     uint64_t pmis_seed;       /* hash seed of the PMIS tie-breaking keys, default 0 */
     int transpose;            /* 1: build the hierarchy on A^T (adjoint solves) */
     int use_x0;               /* 1: mgr_solve starts from the x passed in */
+    int frelax_amg_mask;      /* bit l set: MGR level l relaxes its F-points with one AMG V-cycle on A_FF
+                                 (the paper's F-relaxation of its phase-transition runs, Section 6.2)
+                                 instead of Jacobi; default 0 */
+    int frelax_amg_pre, frelax_amg_post;  /* smoothing sweeps of that V-cycle, default 1, 1 */
 } mgr_options;
 
 typedef struct {
@@ -147,7 +151,8 @@ int mgr_num_levels(mgr_handle *h, int *n_mgr_levels, int *n_amg_levels);
 
 /*
  * Copy one hierarchy matrix to HOST memory.  kind: 0 MGR A_l, 1 MGR P_l,
- * 2 MGR R_l, 3 AMG A_k, 4 AMG P_k, 5 AMG strength pattern S_k (values unset).
+ * 2 MGR R_l, 3 AMG A_k, 4 AMG P_k, 5 AMG strength pattern S_k (values unset),
+ * 6 / 7: A_k / P_k of the F-relaxation AMG of MGR level l, with level = (l << 8) | k.
  * Call with row_ptr == NULL to get the sizes only.  Host arrays: row_ptr
  * int32[nrows + 1], col_idx int32[nnz], values double[nnz] (may be NULL).
  */
@@ -160,7 +165,8 @@ int mgr_get_matrix(mgr_handle *h, int kind, int level, int64_t *nrows, int64_t *
  * (int32, level-local indices), 3 MGR C list_l (int32), 4 AMG C/F marker_k
  * (int32, +1 C / -1 F), 5 AMG l1 row norms_k (double), 6 coarsest LU factors
  * (double n*n row-major, unit-lower L below the diagonal), 7 coarsest LU row
- * permutation (int32).  out == NULL returns the length only in *len.
+ * permutation (int32); 8..11: kinds 4..7 for the F-relaxation AMG of MGR level
+ * l, with level = (l << 8) | k.  out == NULL returns the length only in *len.
  */
 int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len);
 

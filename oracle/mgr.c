@@ -11,7 +11,10 @@
  *   W_r[i,j] = -(a_ij * dinv_j)  (i in C, j in F)   [empty for injective]
  *   P = [W_p; I_C] (rows U_l), R = [W_r, I_C] (columns U_l),
  *   A_{l+1} = R (A_l P), each product by the canonical Gustavson SpGEMM.
- * The last level A_L is handed to classical AMG (amg.c).
+ * The last level A_L is handed to classical AMG (amg.c).  A level may instead
+ * relax its F-points with one AMG V-cycle on A_FF (the paper's F-relaxation
+ * for the saturation-like blocks of its phase-transition runs, Section 6.2):
+ * A_FF = rows and columns F of A_l, numbered in ascending level-local index.
  */
 #include <math.h>
 #include <stdio.h>
@@ -21,6 +24,22 @@
 #include "oracle.h"
 
 typedef struct {
+    orc_mat A, P, PT, S;
+    int32_t *cf;
+    double *l1;
+    float *Af, *Pf, *PTf, *l1f;
+} amg_lev;
+
+/* one classical AMG hierarchy (coarse-grid solver or an F-block solver) */
+typedef struct {
+    amg_lev *lev;
+    int nlev;
+    double *lu;
+    int32_t *perm;
+    int pre, post;
+} amg_hier;
+
+typedef struct {
     orc_mat A, P, R;
     int64_t nF, nC;
     int32_t *flist, *clist; /* U-local indices of F and C points */
@@ -28,14 +47,8 @@ typedef struct {
     int32_t *lab;           /* labels of U_l */
     double *dinv;
     float *Af, *Pf, *Rf, *dinvf;
+    amg_hier *ff;           /* AMG on A_FF for the F-relaxation, or NULL (Jacobi) */
 } mgr_lev;
-
-typedef struct {
-    orc_mat A, P, PT, S;
-    int32_t *cf;
-    double *l1;
-    float *Af, *Pf, *PTf, *l1f;
-} amg_lev;
 
 struct orc_handle {
     int64_t n, ncell;
@@ -45,10 +58,7 @@ struct orc_handle {
     double *binv;
     float *binvf;
     mgr_lev *lev;
-    amg_lev *amg;
-    int namg;
-    double *lu;
-    int32_t *perm;
+    amg_hier cg;            /* coarse-grid AMG on A_L */
     double setup_ms;
 };
 
@@ -67,6 +77,9 @@ void orc_default_opts(orc_opts *o) {
     o->pmis_seed = 0;
     o->precision = 0;
     o->use_x0 = 0;
+    o->frelax_amg_mask = 0;
+    o->frelax_amg_pre = 1;
+    o->frelax_amg_post = 1;
 }
 
 static double now_ms(void) {
@@ -113,6 +126,123 @@ static int validate_csr(const orc_mat *A) {
     return 1;
 }
 
+/* ---------------- classical AMG hierarchy ---------------- */
+
+/* Build the hierarchy on a copy of A: strength -> PMIS -> classical
+ * interpolation -> Galerkin P^T (A P), until n <= coarse_max, the level cap,
+ * an empty or too large (> 0.9 n) coarse set; dense LU on the last level. */
+static int amg_build(amg_hier *H, const orc_mat *A, const orc_opts *o, int pre, int post, char *err, int errlen) {
+    int cap = o->amg_max_levels > 0 ? o->amg_max_levels : 1;
+    if (cap > 64) cap = 64;
+    H->lev = (amg_lev *)calloc(64, sizeof(amg_lev));
+    H->pre = pre;
+    H->post = post;
+    copy_mat(A, &H->lev[0].A);
+    int k = 0;
+    for (;;) {
+        amg_lev *lv = &H->lev[k];
+        int64_t n = lv->A.nrows;
+        int coarsest = (n <= o->amg_coarse_max) || (k == cap - 1);
+        if (!coarsest) {
+            orc_strength(&lv->A, o->amg_theta, &lv->S);
+            lv->cf = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+            orc_pmis(&lv->S, o->pmis_seed, lv->cf);
+            int64_t nc = 0;
+            for (int64_t i = 0; i < n; ++i) nc += lv->cf[i] == 1;
+            if (nc == 0 || nc == n || (double)nc > 0.9 * (double)n) {
+                coarsest = 1;
+            } else {
+                orc_interp(&lv->A, &lv->S, lv->cf, &lv->P);
+                orc_transpose(&lv->P, &lv->PT);
+                orc_mat T;
+                orc_spgemm(&lv->A, &lv->P, &T);
+                orc_spgemm(&lv->PT, &T, &H->lev[k + 1].A);
+                orc_mat_free(&T);
+                lv->l1 = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+                for (int64_t i = 0; i < n; ++i) {
+                    double s = 0.0;
+                    for (int64_t p = lv->A.rp[i]; p < lv->A.rp[i + 1]; ++p) s = s + fabs(lv->A.v[p]);
+                    if (s == 0.0) {
+                        seterr(err, errlen, "AMG: empty row (zero l1 norm)");
+                        H->nlev = k + 1;
+                        return ORC_E_SINGULAR_BLOCK;
+                    }
+                    lv->l1[i] = s;
+                }
+                k++;
+                continue;
+            }
+        }
+        /* coarsest level: dense LU */
+        H->nlev = k + 1;
+        if (n > o->dense_max) {
+            seterr(err, errlen, "AMG coarsening stalled above the dense coarse-solve limit");
+            return ORC_E_INVALID;
+        }
+        H->lu = (double *)calloc((size_t)(n > 0 ? n * n : 1), sizeof(double));
+        H->perm = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t p = lv->A.rp[i]; p < lv->A.rp[i + 1]; ++p) H->lu[i * n + lv->A.ci[p]] = lv->A.v[p];
+        if (orc_dense_lu((int)n, H->lu, H->perm) != ORC_OK) {
+            seterr(err, errlen, "AMG: coarsest matrix is singular");
+            return ORC_E_SINGULAR_BLOCK;
+        }
+        return ORC_OK;
+    }
+}
+
+static void amg_to_f32(amg_hier *H) {
+    for (int k = 0; k + 1 < H->nlev; ++k) {
+        amg_lev *lv = &H->lev[k];
+        lv->Af = to_f32(lv->A.v, lv->A.nnz);
+        lv->Pf = to_f32(lv->P.v, lv->P.nnz);
+        lv->PTf = to_f32(lv->PT.v, lv->PT.nnz);
+        lv->l1f = to_f32(lv->l1, lv->A.nrows);
+    }
+}
+
+static void amg_free(amg_hier *H) {
+    if (!H->lev) return;
+    for (int k = 0; k < 64; ++k) {
+        amg_lev *lv = &H->lev[k];
+        orc_mat_free(&lv->A);
+        orc_mat_free(&lv->P);
+        orc_mat_free(&lv->PT);
+        orc_mat_free(&lv->S);
+        free(lv->cf); free(lv->l1); free(lv->Af); free(lv->Pf); free(lv->PTf); free(lv->l1f);
+    }
+    free(H->lev);
+    free(H->lu);
+    free(H->perm);
+    H->lev = NULL;
+}
+
+/* ---------------- MGR levels ---------------- */
+
+/* rows and columns F of A (F = flist, ascending), renumbered 0..nF-1 */
+static void extract_ff(const orc_mat *A, const int64_t *fmap, const int32_t *flist, int64_t nF, orc_mat *Aff) {
+    Aff->nrows = Aff->ncols = nF;
+    Aff->rp = (int64_t *)calloc((size_t)nF + 1, sizeof(int64_t));
+    for (int64_t f = 0; f < nF; ++f) {
+        int64_t i = flist[f], c = 0;
+        for (int64_t p = A->rp[i]; p < A->rp[i + 1]; ++p) c += fmap[A->ci[p]] >= 0;
+        Aff->rp[f + 1] = Aff->rp[f] + c;
+    }
+    Aff->nnz = Aff->rp[nF];
+    Aff->ci = (int32_t *)malloc((size_t)(Aff->nnz > 0 ? Aff->nnz : 1) * sizeof(int32_t));
+    Aff->v = (double *)malloc((size_t)(Aff->nnz > 0 ? Aff->nnz : 1) * sizeof(double));
+    for (int64_t f = 0; f < nF; ++f) {
+        int64_t i = flist[f], q = Aff->rp[f];
+        for (int64_t p = A->rp[i]; p < A->rp[i + 1]; ++p) {
+            int64_t j = fmap[A->ci[p]];
+            if (j < 0) continue;
+            Aff->ci[q] = (int32_t)j;
+            Aff->v[q] = A->v[p];
+            q++;
+        }
+    }
+}
+
 static int setup_mgr_level(orc_handle *h, int l, char *err, int errlen) {
     mgr_lev *lv = &h->lev[l];
     const orc_mat *A = &lv->A;
@@ -148,6 +278,21 @@ static int setup_mgr_level(orc_handle *h, int l, char *err, int errlen) {
             return ORC_E_ZERO_FDIAG;
         }
         lv->dinv[f] = 1.0 / d;
+    }
+    /* optional AMG on A_FF for the F-relaxation */
+    if ((h->o.frelax_amg_mask >> l) & 1) {
+        if (lv->nF > 0) {
+            orc_mat Aff;
+            extract_ff(A, fmap, lv->flist, lv->nF, &Aff);
+            lv->ff = (amg_hier *)calloc(1, sizeof(amg_hier));
+            int rc = amg_build(lv->ff, &Aff, &h->o, h->o.frelax_amg_pre, h->o.frelax_amg_post, err, errlen);
+            orc_mat_free(&Aff);
+            if (rc != ORC_OK) {
+                free(fmap);
+                free(cmap);
+                return rc;
+            }
+        }
     }
     /* P = [W_p; I_C] */
     orc_mat *P = &lv->P;
@@ -224,75 +369,31 @@ static int setup_mgr_level(orc_handle *h, int l, char *err, int errlen) {
     /* A_{l+1} = R (A P) */
     orc_mat T;
     orc_spgemm(A, P, &T);
-    orc_mat *An = (l + 1 < h->L) ? &h->lev[l + 1].A : &h->amg[0].A;
-    orc_spgemm(R, &T, An);
+    orc_mat An;
+    orc_spgemm(R, &T, &An);
     orc_mat_free(&T);
     if (l + 1 < h->L) {
         mgr_lev *nx = &h->lev[l + 1];
+        nx->A = An;
         nx->lab = (int32_t *)malloc((size_t)(lv->nC > 0 ? lv->nC : 1) * sizeof(int32_t));
         nx->glob = (int32_t *)malloc((size_t)(lv->nC > 0 ? lv->nC : 1) * sizeof(int32_t));
         for (int64_t c = 0; c < lv->nC; ++c) {
             nx->lab[c] = lv->lab[lv->clist[c]];
             nx->glob[c] = lv->glob[lv->clist[c]];
         }
+    } else {
+        /* the last reduction's coarse operator goes to the coarse-grid AMG */
+        int rc = amg_build(&h->cg, &An, &h->o, h->o.amg_pre, h->o.amg_post, err, errlen);
+        orc_mat_free(&An);
+        if (rc != ORC_OK) {
+            free(fmap);
+            free(cmap);
+            return rc;
+        }
     }
     free(fmap);
     free(cmap);
     return ORC_OK;
-}
-
-static int setup_amg(orc_handle *h, char *err, int errlen) {
-    int cap = h->o.amg_max_levels > 0 ? h->o.amg_max_levels : 1;
-    int k = 0;
-    for (;;) {
-        amg_lev *lv = &h->amg[k];
-        int64_t n = lv->A.nrows;
-        int coarsest = (n <= h->o.amg_coarse_max) || (k == cap - 1);
-        if (!coarsest) {
-            orc_strength(&lv->A, h->o.amg_theta, &lv->S);
-            lv->cf = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-            orc_pmis(&lv->S, h->o.pmis_seed, lv->cf);
-            int64_t nc = 0;
-            for (int64_t i = 0; i < n; ++i) nc += lv->cf[i] == 1;
-            if (nc == 0 || nc == n || (double)nc > 0.9 * (double)n) {
-                coarsest = 1;
-            } else {
-                orc_interp(&lv->A, &lv->S, lv->cf, &lv->P);
-                orc_transpose(&lv->P, &lv->PT);
-                orc_mat T;
-                orc_spgemm(&lv->A, &lv->P, &T);
-                orc_spgemm(&lv->PT, &T, &h->amg[k + 1].A);
-                orc_mat_free(&T);
-                lv->l1 = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-                for (int64_t i = 0; i < n; ++i) {
-                    double s = 0.0;
-                    for (int64_t p = lv->A.rp[i]; p < lv->A.rp[i + 1]; ++p) s = s + fabs(lv->A.v[p]);
-                    if (s == 0.0) {
-                        seterr(err, errlen, "AMG: empty row (zero l1 norm)");
-                        return ORC_E_SINGULAR_BLOCK;
-                    }
-                    lv->l1[i] = s;
-                }
-                k++;
-                continue;
-            }
-        }
-        /* coarsest level: dense LU */
-        h->namg = k + 1;
-        if (n > h->o.dense_max) {
-            seterr(err, errlen, "AMG coarsening stalled above the dense coarse-solve limit");
-            return ORC_E_INVALID;
-        }
-        h->lu = (double *)calloc((size_t)(n > 0 ? n * n : 1), sizeof(double));
-        h->perm = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
-        for (int64_t i = 0; i < n; ++i)
-            for (int64_t p = lv->A.rp[i]; p < lv->A.rp[i + 1]; ++p) h->lu[i * n + lv->A.ci[p]] = lv->A.v[p];
-        if (orc_dense_lu((int)n, h->lu, h->perm) != ORC_OK) {
-            seterr(err, errlen, "AMG: coarsest matrix is singular");
-            return ORC_E_SINGULAR_BLOCK;
-        }
-        return ORC_OK;
-    }
 }
 
 int orc_setup(const orc_mat *A, int bs, const int32_t *labels, const orc_opts *o, orc_handle **out,
@@ -320,9 +421,7 @@ int orc_setup(const orc_mat *A, int bs, const int32_t *labels, const orc_opts *o
     h->o = *o;
     copy_mat(A, &h->A0);
     h->lev = (mgr_lev *)calloc((size_t)(L > 0 ? L : 1), sizeof(mgr_lev));
-    h->amg = (amg_lev *)calloc(64, sizeof(amg_lev));
     int rc = ORC_OK;
-    if (h->o.amg_max_levels > 64) h->o.amg_max_levels = 64;
     if (o->global_relax && L > 0) {
         h->binv = (double *)malloc((size_t)h->ncell * bs * bs * sizeof(double));
         if (orc_block_inverse(h->ncell, bs, A, h->binv) != ORC_OK) {
@@ -340,9 +439,8 @@ int orc_setup(const orc_mat *A, int bs, const int32_t *labels, const orc_opts *o
         }
         for (int l = 0; l < L && rc == ORC_OK; ++l) rc = setup_mgr_level(h, l, err, errlen);
     } else if (rc == ORC_OK) {
-        copy_mat(A, &h->amg[0].A);
+        rc = amg_build(&h->cg, A, &h->o, h->o.amg_pre, h->o.amg_post, err, errlen);
     }
-    if (rc == ORC_OK) rc = setup_amg(h, err, errlen);
     if (rc == ORC_OK && o->precision == 1) {
         for (int l = 0; l < L; ++l) {
             mgr_lev *lv = &h->lev[l];
@@ -350,14 +448,9 @@ int orc_setup(const orc_mat *A, int bs, const int32_t *labels, const orc_opts *o
             lv->Pf = to_f32(lv->P.v, lv->P.nnz);
             lv->Rf = to_f32(lv->R.v, lv->R.nnz);
             lv->dinvf = to_f32(lv->dinv, lv->nF);
+            if (lv->ff) amg_to_f32(lv->ff);
         }
-        for (int k = 0; k + 1 < h->namg; ++k) {
-            amg_lev *lv = &h->amg[k];
-            lv->Af = to_f32(lv->A.v, lv->A.nnz);
-            lv->Pf = to_f32(lv->P.v, lv->P.nnz);
-            lv->PTf = to_f32(lv->PT.v, lv->PT.nnz);
-            lv->l1f = to_f32(lv->l1, lv->A.nrows);
-        }
+        amg_to_f32(&h->cg);
         if (h->binv) h->binvf = to_f32(h->binv, h->ncell * bs * bs);
     }
     if (rc != ORC_OK) {
@@ -379,21 +472,15 @@ int orc_destroy(orc_handle *h) {
         orc_mat_free(&lv->R);
         free(lv->flist); free(lv->clist); free(lv->glob); free(lv->lab); free(lv->dinv);
         free(lv->Af); free(lv->Pf); free(lv->Rf); free(lv->dinvf);
+        if (lv->ff) {
+            amg_free(lv->ff);
+            free(lv->ff);
+        }
     }
-    for (int k = 0; k < 64; ++k) {
-        amg_lev *lv = &h->amg[k];
-        orc_mat_free(&lv->A);
-        orc_mat_free(&lv->P);
-        orc_mat_free(&lv->PT);
-        orc_mat_free(&lv->S);
-        free(lv->cf); free(lv->l1); free(lv->Af); free(lv->Pf); free(lv->PTf); free(lv->l1f);
-    }
+    amg_free(&h->cg);
     free(h->lev);
-    free(h->amg);
     free(h->binv);
     free(h->binvf);
-    free(h->lu);
-    free(h->perm);
     free(h);
     return ORC_OK;
 }
@@ -458,14 +545,14 @@ int orc_solve(orc_handle *h, const double *b, double *x, double tol, orc_stats *
     st->iterations = 0;
     st->res_history_len = 0;
     st->setup_ms = h->setup_ms;
-    st->n_levels = h->L + h->namg;
+    st->n_levels = h->L + h->cg.nlev;
     for (int l = 0; l < h->L && l < 64; ++l) {
         st->level_n[l] = h->lev[l].A.nrows;
         st->level_nnz[l] = h->lev[l].A.nnz;
     }
-    for (int k = 0; k < h->namg && h->L + k < 64; ++k) {
-        st->level_n[h->L + k] = h->amg[k].A.nrows;
-        st->level_nnz[h->L + k] = h->amg[k].A.nnz;
+    for (int k = 0; k < h->cg.nlev && h->L + k < 64; ++k) {
+        st->level_n[h->L + k] = h->cg.lev[k].A.nrows;
+        st->level_nnz[h->L + k] = h->cg.lev[k].A.nnz;
     }
     double bnorm = sqrt(dot(n, b, b));
     if (!isfinite(bnorm)) {
@@ -557,9 +644,24 @@ int orc_solve(orc_handle *h, const double *b, double *x, double tol, orc_stats *
     return status;
 }
 
-/* ---- introspection ---- */
+/* ---- introspection ----
+ * For the F-relaxation AMG of MGR level l, the level argument is (l << 8) | k. */
 int orc_num_mgr_levels(orc_handle *h) { return h->L; }
-int orc_num_amg_levels(orc_handle *h) { return h->namg; }
+int orc_num_amg_levels(orc_handle *h) { return h->cg.nlev; }
+int orc_num_ff_levels(orc_handle *h, int l) {
+    if (l < 0 || l >= h->L || !h->lev[l].ff) return 0;
+    return h->lev[l].ff->nlev;
+}
+
+static amg_hier *hier_of(orc_handle *h, int ff_kind, int *level) {
+    if (ff_kind) {
+        int l = *level >> 8;
+        *level &= 0xff;
+        if (l < 0 || l >= h->L || !h->lev[l].ff) return NULL;
+        return h->lev[l].ff;
+    }
+    return &h->cg;
+}
 
 int orc_get_mat(orc_handle *h, int kind, int level, orc_mat *out) {
     const orc_mat *m = NULL;
@@ -567,11 +669,12 @@ int orc_get_mat(orc_handle *h, int kind, int level, orc_mat *out) {
         if (level < 0 || level >= h->L) return ORC_E_INVALID;
         m = kind == 0 ? &h->lev[level].A : kind == 1 ? &h->lev[level].P : &h->lev[level].R;
     } else {
-        if (level < 0 || level >= h->namg) return ORC_E_INVALID;
-        if (kind == 3) m = &h->amg[level].A;
-        else if (level >= h->namg - 1) return ORC_E_INVALID;
-        else if (kind == 4) m = &h->amg[level].P;
-        else if (kind == 5) m = &h->amg[level].S;
+        amg_hier *H = hier_of(h, kind >= 6, &level);
+        if (!H || level < 0 || level >= H->nlev) return ORC_E_INVALID;
+        if (kind == 3 || kind == 6) m = &H->lev[level].A;
+        else if (level >= H->nlev - 1) return ORC_E_INVALID;
+        else if (kind == 4 || kind == 7) m = &H->lev[level].P;
+        else if (kind == 5) m = &H->lev[level].S;
         else return ORC_E_INVALID;
     }
     *out = *m; /* a view: the handle keeps ownership */
@@ -579,14 +682,18 @@ int orc_get_mat(orc_handle *h, int kind, int level, orc_mat *out) {
 }
 
 int64_t orc_get_vec_len(orc_handle *h, int kind, int level) {
-    switch (kind) {
-    case 0: return h->binv ? h->ncell * h->bs * h->bs : 0;
-    case 1: case 2: return (level >= 0 && level < h->L) ? h->lev[level].nF : -1;
-    case 3: return (level >= 0 && level < h->L) ? h->lev[level].nC : -1;
-    case 4: return (level >= 0 && level < h->namg - 1) ? h->amg[level].A.nrows : -1;
-    case 5: return (level >= 0 && level < h->namg - 1) ? h->amg[level].A.nrows : -1;
-    case 6: { int64_t n = h->amg[h->namg - 1].A.nrows; return n * n; }
-    case 7: return h->amg[h->namg - 1].A.nrows;
+    if (kind == 0) return h->binv ? h->ncell * h->bs * h->bs : 0;
+    if (kind >= 1 && kind <= 3) {
+        if (level < 0 || level >= h->L) return -1;
+        return kind == 3 ? h->lev[level].nC : h->lev[level].nF;
+    }
+    int base = (kind >= 8) ? kind - 4 : kind; /* 8..11 mirror 4..7 for an F-block AMG */
+    amg_hier *H = hier_of(h, kind >= 8, &level);
+    if (!H) return -1;
+    switch (base) {
+    case 4: case 5: return (level >= 0 && level < H->nlev - 1) ? H->lev[level].A.nrows : -1;
+    case 6: { int64_t n = H->lev[H->nlev - 1].A.nrows; return n * n; }
+    case 7: return H->lev[H->nlev - 1].A.nrows;
     }
     return -1;
 }
@@ -594,15 +701,17 @@ int64_t orc_get_vec_len(orc_handle *h, int kind, int level) {
 int orc_get_vec(orc_handle *h, int kind, int level, void *out) {
     int64_t len = orc_get_vec_len(h, kind, level);
     if (len < 0) return ORC_E_INVALID;
-    switch (kind) {
-    case 0: memcpy(out, h->binv, (size_t)len * sizeof(double)); break;
-    case 1: memcpy(out, h->lev[level].dinv, (size_t)len * sizeof(double)); break;
-    case 2: memcpy(out, h->lev[level].flist, (size_t)len * sizeof(int32_t)); break;
-    case 3: memcpy(out, h->lev[level].clist, (size_t)len * sizeof(int32_t)); break;
-    case 4: memcpy(out, h->amg[level].cf, (size_t)len * sizeof(int32_t)); break;
-    case 5: memcpy(out, h->amg[level].l1, (size_t)len * sizeof(double)); break;
-    case 6: memcpy(out, h->lu, (size_t)len * sizeof(double)); break;
-    case 7: memcpy(out, h->perm, (size_t)len * sizeof(int32_t)); break;
+    if (kind == 0) { memcpy(out, h->binv, (size_t)len * sizeof(double)); return ORC_OK; }
+    if (kind == 1) { memcpy(out, h->lev[level].dinv, (size_t)len * sizeof(double)); return ORC_OK; }
+    if (kind == 2) { memcpy(out, h->lev[level].flist, (size_t)len * sizeof(int32_t)); return ORC_OK; }
+    if (kind == 3) { memcpy(out, h->lev[level].clist, (size_t)len * sizeof(int32_t)); return ORC_OK; }
+    int base = (kind >= 8) ? kind - 4 : kind;
+    amg_hier *H = hier_of(h, kind >= 8, &level);
+    switch (base) {
+    case 4: memcpy(out, H->lev[level].cf, (size_t)len * sizeof(int32_t)); break;
+    case 5: memcpy(out, H->lev[level].l1, (size_t)len * sizeof(double)); break;
+    case 6: memcpy(out, H->lu, (size_t)len * sizeof(double)); break;
+    case 7: memcpy(out, H->perm, (size_t)len * sizeof(int32_t)); break;
     }
     return ORC_OK;
 }

@@ -46,6 +46,8 @@ typedef struct {
     uint64_t pmis_seed;
     int precision;        /* 0 FP64 preconditioner, 1 FP32 preconditioner */
     int use_x0;
+    int frelax_amg_mask;  /* bit l set: F-relaxation of MGR level l by one AMG V-cycle on A_FF */
+    int frelax_amg_pre, frelax_amg_post;
 } orc_opts;
 
 typedef struct {
@@ -88,11 +90,14 @@ int orc_pattern_outer(const orc_mat *A, const double *lambda, const double *x, d
 /* --- introspection of a built hierarchy --- */
 int orc_num_mgr_levels(orc_handle *h);
 int orc_num_amg_levels(orc_handle *h);
-/* kind: 0 MGR A_l, 1 MGR P_l, 2 MGR R_l, 3 AMG A_k, 4 AMG P_k, 5 AMG strength S_k */
+int orc_num_ff_levels(orc_handle *h, int l);
+/* kind: 0 MGR A_l, 1 MGR P_l, 2 MGR R_l, 3 AMG A_k, 4 AMG P_k, 5 AMG strength S_k,
+ *       6 F-block AMG A_k of MGR level l, 7 its P_k (level argument (l << 8) | k) */
 int orc_get_mat(orc_handle *h, int kind, int level, orc_mat *out_view);
 /* kind: 0 block inverses (9 per cell), 1 MGR dinv_l, 2 MGR F list_l, 3 MGR C list_l,
  *       4 AMG C/F marker_k (+1 C, -1 F), 5 AMG l1 diagonal_k, 6 coarsest LU (n*n),
- *       7 coarsest LU row permutation */
+ *       7 coarsest LU row permutation; 8..11 the same as 4..7 for the F-block AMG of
+ *       MGR level l (level argument (l << 8) | k) */
 int64_t orc_get_vec_len(orc_handle *h, int kind, int level);
 int orc_get_vec(orc_handle *h, int kind, int level, void *out);
 

@@ -31,7 +31,8 @@ class _Opts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_iter", C.c_int), ("rp_type", C.c_int), ("global_relax", C.c_int),
                 ("f_sweeps", C.c_int), ("amg_theta", C.c_double), ("amg_pre", C.c_int), ("amg_post", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_coarse_max", C.c_int), ("dense_max", C.c_int),
-                ("pmis_seed", C.c_uint64), ("precision", C.c_int), ("use_x0", C.c_int)]
+                ("pmis_seed", C.c_uint64), ("precision", C.c_int), ("use_x0", C.c_int),
+                ("frelax_amg_mask", C.c_int), ("frelax_amg_pre", C.c_int), ("frelax_amg_post", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -75,6 +76,7 @@ def lib():
         L.orc_pattern_outer.argtypes = [P(_Mat), C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_num_mgr_levels.argtypes = [C.c_void_p]
         L.orc_num_amg_levels.argtypes = [C.c_void_p]
+        L.orc_num_ff_levels.argtypes = [C.c_void_p, C.c_int]
         L.orc_get_mat.argtypes = [C.c_void_p, C.c_int, C.c_int, P(_Mat)]
         L.orc_get_vec_len.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.orc_get_vec_len.restype = C.c_int64
@@ -221,7 +223,7 @@ def pattern_outer(A: CSR, lam, x):
 
 DEFAULTS = dict(restart=30, max_iter=400, rp_type=0, global_relax=1, f_sweeps=1, amg_theta=0.25, amg_pre=2,
                 amg_post=2, amg_max_levels=25, amg_coarse_max=64, dense_max=4096, pmis_seed=0, precision=0,
-                use_x0=0)
+                use_x0=0, frelax_amg_mask=0, frelax_amg_pre=1, frelax_amg_post=1)
 
 
 class OracleError(RuntimeError):
@@ -317,6 +319,21 @@ class Oracle:
             d.update(P=self._mat_view(4, k), S=self._mat_view(5, k), cf=self._vec(4, k, np.int32),
                      l1=self._vec(5, k, np.float64))
         return d
+
+    def n_ff_levels(self, l):
+        return lib().orc_num_ff_levels(self.h, l)
+
+    def ff_level(self, l, k):
+        """F-relaxation AMG hierarchy of MGR level l, level k."""
+        code = (l << 8) | k
+        d = dict(A=self._mat_view(6, code))
+        if k < self.n_ff_levels(l) - 1:
+            d.update(P=self._mat_view(7, code), cf=self._vec(8, code, np.int32), l1=self._vec(9, code, np.float64))
+        return d
+
+    def ff_coarse_lu(self, l):
+        n = self.ff_level(l, self.n_ff_levels(l) - 1)["A"].shape[0]
+        return self._vec(10, l << 8, np.float64).reshape(n, n), self._vec(11, l << 8, np.int32)
 
     def block_inverses(self):
         return self._vec(0, 0, np.float64)

@@ -1,15 +1,16 @@
 /*
  * Oracle MGR V-cycle, written once and instantiated twice by mgr.c:
  * REAL = double (FP64 preconditioner) and REAL = float (the FP32 hierarchy of
- * the mixed-precision form).  The coarsest dense solve is FP64 in both.
+ * the mixed-precision form).  The coarsest dense solves are FP64 in both.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
  * MGR(l, r) follows the paper's algorithm "MGR preconditioner with
  * presmoothing" (Section 4) applied recursively over the reduction levels of
  * Section 5, i.e. the error propagator of eq. MGR-pre,
  *   I - M^{-1} A = (I - P M_c^{-1} R A)(I - M_f^{-1} A),
- * with M_f = global block relaxation (level 0 only) followed by F-point Jacobi
- * with diag(A_FF), and M_c = the next level (AMG V-cycle at the last level).
+ * with M_f = global block relaxation (level 0 only) followed by F-relaxation
+ * (Jacobi with diag(A_FF), or one AMG V-cycle on A_FF), and M_c = the next
+ * level (AMG V-cycle at the last level).
  */
 
 /* y = r - M x over rows [0, nrows), values taken from vals */
@@ -39,14 +40,15 @@ static void FN(spmv_add)(const orc_mat *M, const REAL *vals, const REAL *x, REAL
     }
 }
 
-static void FN(amg_cycle)(orc_handle *h, int k, const REAL *r, REAL *x) {
-    amg_lev *lv = &h->amg[k];
+/* classical AMG V(pre, post) cycle from x = 0 with l1-Jacobi smoothing */
+static void FN(amg_cycle)(const amg_hier *H, int k, const REAL *r, REAL *x) {
+    const amg_lev *lv = &H->lev[k];
     int64_t n = lv->A.nrows;
-    if (k == h->namg - 1) {
+    if (k == H->nlev - 1) {
         double *rd = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
         double *xd = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
         for (int64_t i = 0; i < n; ++i) rd[i] = (double)r[i];
-        orc_dense_lu_solve((int)n, h->lu, h->perm, rd, xd);
+        orc_dense_lu_solve((int)n, H->lu, H->perm, rd, xd);
         for (int64_t i = 0; i < n; ++i) x[i] = (REAL)xd[i];
         free(rd);
         free(xd);
@@ -60,17 +62,17 @@ static void FN(amg_cycle)(orc_handle *h, int k, const REAL *r, REAL *x) {
     REAL *ec = (REAL *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(REAL));
     for (int64_t i = 0; i < n; ++i) x[i] = 0;
     /* pre-smoothing: l1-Jacobi, x += (r - A x) / d_l1 */
-    for (int s = 0; s < h->o.amg_pre; ++s) {
+    for (int s = 0; s < H->pre; ++s) {
         FN(residual)(&lv->A, Av, r, x, t);
         for (int64_t i = 0; i < n; ++i) x[i] = x[i] + t[i] / l1[i];
     }
     /* coarse-grid correction x += P M_c^{-1} P^T (r - A x) */
     FN(residual)(&lv->A, Av, r, x, t);
     FN(spmv)(&lv->PT, VALS(lv->PT, lv->PTf), t, rc);
-    FN(amg_cycle)(h, k + 1, rc, ec);
+    FN(amg_cycle)(H, k + 1, rc, ec);
     FN(spmv_add)(&lv->P, VALS(lv->P, lv->Pf), ec, x);
     /* post-smoothing */
-    for (int s = 0; s < h->o.amg_post; ++s) {
+    for (int s = 0; s < H->post; ++s) {
         FN(residual)(&lv->A, Av, r, x, t);
         for (int64_t i = 0; i < n; ++i) x[i] = x[i] + t[i] / l1[i];
     }
@@ -81,7 +83,7 @@ static void FN(amg_cycle)(orc_handle *h, int k, const REAL *r, REAL *x) {
 
 static void FN(mgr_cycle)(orc_handle *h, int l, const REAL *r, REAL *e) {
     if (l == h->L) {
-        FN(amg_cycle)(h, 0, r, e);
+        FN(amg_cycle)(&h->cg, 0, r, e);
         return;
     }
     mgr_lev *lv = &h->lev[l];
@@ -92,6 +94,7 @@ static void FN(mgr_cycle)(orc_handle *h, int l, const REAL *r, REAL *e) {
     REAL *rc = (REAL *)malloc((size_t)(nC > 0 ? nC : 1) * sizeof(REAL));
     REAL *ec = (REAL *)malloc((size_t)(nC > 0 ? nC : 1) * sizeof(REAL));
     REAL *tf = (REAL *)malloc((size_t)(nF > 0 ? nF : 1) * sizeof(REAL));
+    REAL *df = (REAL *)malloc((size_t)(nF > 0 ? nF : 1) * sizeof(REAL));
     for (int64_t i = 0; i < nU; ++i) e[i] = 0;
     /* (1) global relaxation e = blockdiag(A)^{-1} r (level 0 only) */
     if (l == 0 && h->o.global_relax) {
@@ -106,7 +109,8 @@ static void FN(mgr_cycle)(orc_handle *h, int l, const REAL *r, REAL *e) {
             for (int64_t c = 0; c < h->ncell; ++c) e[c] = bi[c] * r[c];
         }
     }
-    /* (2) F-relaxation: Jacobi with diag(A_FF), e_F += D_FF^{-1} (r - A e)_F */
+    /* (2) F-relaxation: e_F += M_FF^{-1} (r - A e)_F with M_FF = diag(A_FF)
+     *     (Jacobi) or one AMG V-cycle on A_FF */
     for (int s = 0; s < h->o.f_sweeps; ++s) {
         for (int64_t f = 0; f < nF; ++f) {
             int64_t i = lv->flist[f];
@@ -114,7 +118,12 @@ static void FN(mgr_cycle)(orc_handle *h, int l, const REAL *r, REAL *e) {
             for (int64_t p = lv->A.rp[i]; p < lv->A.rp[i + 1]; ++p) acc += Av[p] * e[lv->A.ci[p]];
             tf[f] = r[i] - acc;
         }
-        for (int64_t f = 0; f < nF; ++f) e[lv->flist[f]] = e[lv->flist[f]] + dinv[f] * tf[f];
+        if (lv->ff) {
+            FN(amg_cycle)(lv->ff, 0, tf, df);
+            for (int64_t f = 0; f < nF; ++f) e[lv->flist[f]] = e[lv->flist[f]] + df[f];
+        } else {
+            for (int64_t f = 0; f < nF; ++f) e[lv->flist[f]] = e[lv->flist[f]] + dinv[f] * tf[f];
+        }
     }
     /* (3) coarse-grid correction e += P M_c^{-1} R (r - A e) */
     FN(residual)(&lv->A, Av, r, e, rho);
@@ -125,4 +134,5 @@ static void FN(mgr_cycle)(orc_handle *h, int l, const REAL *r, REAL *e) {
     free(rc);
     free(ec);
     free(tf);
+    free(df);
 }

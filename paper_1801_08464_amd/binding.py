@@ -32,7 +32,8 @@ class MgrOptions(C.Structure):
                 ("rp_type", C.c_int), ("global_relax", C.c_int), ("f_sweeps", C.c_int), ("amg_theta", C.c_double),
                 ("amg_pre", C.c_int), ("amg_post", C.c_int), ("amg_max_levels", C.c_int),
                 ("amg_coarse_max", C.c_int), ("dense_max", C.c_int), ("pmis_seed", C.c_uint64),
-                ("transpose", C.c_int), ("use_x0", C.c_int)]
+                ("transpose", C.c_int), ("use_x0", C.c_int), ("frelax_amg_mask", C.c_int),
+                ("frelax_amg_pre", C.c_int), ("frelax_amg_post", C.c_int)]
 
 
 class MgrStats(C.Structure):

@@ -125,15 +125,20 @@ __global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, doubl
 // stage 1: WN = <w,w> after the update; guard = 1 if WN < WN0 / 2 (DGKS test)
 // stage 2: second pass (only when guard): H(:,j) += h_i, hcur = h_i
 // stage 3: WN = <w,w> after the second update
+// One block per reduced value (blockIdx.x = i); each sums its nblk partials with a
+// fixed thread/tree order, so the result does not depend on scheduling.
 __global__ void __launch_bounds__(BT) k_arnoldi_fin(int stage, int j, int m, int nblk, const double *__restrict__ part,
                                                     double *__restrict__ dsc, int *guard) {
     if ((stage == 2 || stage == 3) && *guard == 0) return;
+    __shared__ double sh[BT / kWave];
     const int t = threadIdx.x;
+    const int i = blockIdx.x;
     if (stage == 0 || stage == 2) {
         const int nv = j + 1;
-        for (int i = t; i <= nv; i += BT) {
-            double s = 0.0;
-            for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * (nv + 1) + i];
+        double s = 0.0;
+        for (int b = t; b < nblk; b += BT) s += part[(int64_t)b * (nv + 1) + i];
+        s = block_sum(s, sh);
+        if (t == 0) {
             if (i < nv) {
                 if (stage == 0) dsc[Dsc::H(i, j, m)] = s;
                 else dsc[Dsc::H(i, j, m)] += s;
@@ -142,11 +147,14 @@ __global__ void __launch_bounds__(BT) k_arnoldi_fin(int stage, int j, int m, int
                 dsc[Dsc::WN0] = s;
             }
         }
-    } else if (t == 0) {
+    } else {
         double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[b];
-        dsc[Dsc::WN] = s;
-        if (stage == 1) *guard = (s < 0.5 * dsc[Dsc::WN0]) ? 1 : 0;
+        for (int b = t; b < nblk; b += BT) s += part[b];
+        s = block_sum(s, sh);
+        if (t == 0) {
+            dsc[Dsc::WN] = s;
+            if (stage == 1) *guard = (s < 0.5 * dsc[Dsc::WN0]) ? 1 : 0;
+        }
     }
 }
 
@@ -189,10 +197,11 @@ __global__ void k_trisolve(int k, int m, double *dsc) {
 }
 
 __global__ void __launch_bounds__(BT) k_norm_fin(int nblk, const double *__restrict__ part, double *out) {
-    if (threadIdx.x != 0) return;
+    __shared__ double sh[BT / kWave];
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[b];
-    out[0] = sqrt(s);
+    for (int b = threadIdx.x; b < nblk; b += BT) s += part[b];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[0] = sqrt(s);
 }
 
 }  // namespace
@@ -247,7 +256,8 @@ void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hip
 
 void launch_arnoldi_fin(int stage, int j, int m, int nblk, const double *part, double *dsc, int *guard,
                         hipStream_t s) {
-    k_arnoldi_fin<<<1, BT, 0, s>>>(stage, j, m, nblk, part, dsc, guard);
+    const unsigned g = (stage == 0 || stage == 2) ? (unsigned)(j + 2) : 1u;
+    k_arnoldi_fin<<<g, BT, 0, s>>>(stage, j, m, nblk, part, dsc, guard);
 }
 
 void launch_givens(int j, int m, double *dsc, hipStream_t s) { k_givens<<<1, 64, 0, s>>>(j, m, dsc); }
@@ -255,7 +265,7 @@ void launch_givens(int j, int m, double *dsc, hipStream_t s) { k_givens<<<1, 64,
 void launch_trisolve(int k, int m, double *dsc, hipStream_t s) { k_trisolve<<<1, 64, 0, s>>>(k, m, dsc); }
 
 void launch_norm_fin(int nblk, const double *part, double *out, hipStream_t s) {
-    k_norm_fin<<<1, 64, 0, s>>>(nblk, part, out);
+    k_norm_fin<<<1, BT, 0, s>>>(nblk, part, out);
 }
 
 int red_blocks(int64_t n) { return (int)red_grid(n); }

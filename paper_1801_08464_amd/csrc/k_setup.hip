@@ -261,6 +261,32 @@ __global__ void k_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, 
     if (i < n) dst[i] = src[idx[i]];
 }
 
+// A_FF: the F rows of A restricted to F columns, renumbered by fmap (order kept)
+__global__ void k_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci,
+                           const int32_t *fmap, int32_t *cnt) {
+    int64_t f = gtid();
+    if (f >= nF) return;
+    int64_t i = flist[f];
+    int c = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) c += fmap[ci[p]] >= 0;
+    cnt[f] = c;
+}
+
+__global__ void k_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
+                          const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv) {
+    int64_t f = gtid();
+    if (f >= nF) return;
+    int64_t i = flist[f];
+    int q = Frp[f];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = fmap[ci[p]];
+        if (j < 0) continue;
+        Fci[q] = j;
+        Fv[q] = v[p];
+        q++;
+    }
+}
+
 // ---------------- SpGEMM: one wavefront per output row ----------------
 // Lane l holds the entries t = l, l+64, ... of row i of A (ascending k) and a
 // cursor into row k of B.  Each step takes the smallest head column j over the
@@ -741,6 +767,14 @@ void launch_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, const in
 }
 void launch_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst, hipStream_t s) {
     if (n > 0) k_gather_i32<<<nblocks(n, BT), BT, 0, s>>>(n, idx, src, dst);
+}
+void launch_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
+                     int32_t *cnt, hipStream_t s) {
+    if (nF > 0) k_ff_count<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, fmap, cnt);
+}
+void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
+                    const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s) {
+    if (nF > 0) k_ff_fill<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, v, fmap, Frp, Fci, Fv);
 }
 int spgemm_max_row() { return kWave * kSpgChunks; }
 void launch_spgemm(int pass, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,

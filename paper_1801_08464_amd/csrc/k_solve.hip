@@ -147,6 +147,20 @@ __global__ void k_div(int64_t n, const T *__restrict__ r, const T *__restrict__ 
     if (i < n) x[i] = r[i] / d[i];
 }
 
+template <typename T>
+__global__ void k_gather(int64_t n, const int32_t *__restrict__ idx, const T *__restrict__ src, T *__restrict__ dst) {
+    const int64_t i = gtid();
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+template <typename T>
+__global__ void k_scatter_add(int64_t n, const int32_t *__restrict__ idx, const T *__restrict__ d, T *__restrict__ e) {
+    const int64_t i = gtid();
+    if (i >= n) return;
+    const int64_t j = idx[i];
+    e[j] = e[j] + d[i];
+}
+
 // forward/back substitution with the coarsest LU (FP64 throughout); one workgroup
 template <typename T>
 __global__ void __launch_bounds__(256) k_lu_solve(int64_t n, const double *__restrict__ lu,
@@ -265,6 +279,16 @@ void launch_div(int64_t n, const T *r, const T *d, T *x, hipStream_t s) {
 }
 
 template <typename T>
+void launch_gather(int64_t n, const int32_t *idx, const T *src, T *dst, hipStream_t s) {
+    if (n > 0) k_gather<T><<<nblocks(n, BT), BT, 0, s>>>(n, idx, src, dst);
+}
+
+template <typename T>
+void launch_scatter_add(int64_t n, const int32_t *idx, const T *d, T *e, hipStream_t s) {
+    if (n > 0) k_scatter_add<T><<<nblocks(n, BT), BT, 0, s>>>(n, idx, d, e);
+}
+
+template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s) {
     if (n > 0) k_lu_solve<T><<<1, BT, (size_t)n * sizeof(double), s>>>(n, lu, perm, b, x);
 }
@@ -280,6 +304,8 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
     template void launch_frelax_first<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);     \
     template void launch_frelax_scatter<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);   \
     template void launch_div<T>(int64_t, const T *, const T *, T *, hipStream_t);                               \
+    template void launch_gather<T>(int64_t, const int32_t *, const T *, T *, hipStream_t);                      \
+    template void launch_scatter_add<T>(int64_t, const int32_t *, const T *, T *, hipStream_t);                 \
     template void launch_lu_solve<T>(int64_t, const double *, const int32_t *, const T *, T *, hipStream_t);
 
 MGR_INSTANTIATE(double)

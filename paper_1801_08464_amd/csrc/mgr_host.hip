@@ -159,6 +159,8 @@ void build_csell(mgr_handle *h) {
     launch_csell_fill(S.ncell, S.bs, A.rp, A.ci, A.v, S.off, S.width, S.col, S.v, h->stream);
 }
 
+void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post);
+
 void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int32_t *&glob_next) {
     MgrLevel &lv = h->lev[l];
     const DCsr &A = lv.A;
@@ -185,6 +187,20 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
         throw_err(h, MGR_E_ZERO_FDIAG, msg);
     }
     lv.aff_diag = h->herr[5] == 0;
+    // optional F-relaxation by one AMG V-cycle on A_FF
+    if (((h->o.frelax_amg_mask >> l) & 1) && lv.nF > 0) {
+        Tmp<int32_t> cnt(h, lv.nF);
+        DCsr Aff;
+        Aff.nrows = Aff.ncols = lv.nF;
+        launch_ff_count(lv.nF, lv.flist, A.rp, A.ci, lv.fmap, cnt.p, h->stream);
+        Aff.rp = dalloc<int32_t>(h, lv.nF + 1);
+        Aff.nnz = scan(h, cnt.p, Aff.rp, lv.nF);
+        Aff.ci = dalloc<int32_t>(h, Aff.nnz);
+        Aff.v = dalloc<double>(h, Aff.nnz);
+        launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, Aff.rp, Aff.ci, Aff.v, h->stream);
+        lv.ff = std::make_shared<AmgHier>();
+        build_amg(h, *lv.ff, Aff, h->o.frelax_amg_pre, h->o.frelax_amg_post);
+    }
     const int rp_type = h->o.rp_type;
     // P = [W_p; I]
     {
@@ -229,12 +245,16 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     launch_gather_i32(lv.nC, lv.clist, lv.glob, glob_next, h->stream);
 }
 
-void build_amg(mgr_handle *h, const DCsr &Atop) {
+// Classical AMG hierarchy on Atop (kept as its level 0): strength -> PMIS ->
+// classical interpolation -> Galerkin P^T (A P), down to a dense LU.
+void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
     const mgr_options &o = h->o;
+    H.pre = pre;
+    H.post = post;
     DCsr A = Atop;
     for (int k = 0;; ++k) {
-        h->amg.emplace_back();
-        AmgLevel &lv = h->amg.back();
+        H.lev.emplace_back();
+        AmgLevel &lv = H.lev.back();
         lv.A = A;
         lv.n = A.nrows;
         const int64_t n = A.nrows;
@@ -306,11 +326,11 @@ void build_amg(mgr_handle *h, const DCsr &Atop) {
         if (n > o.dense_max)
             throw_err(h, MGR_E_INVALID, "AMG coarsening stalled at " + std::to_string(n) +
                                             " unknowns, above the dense coarse-solve limit");
-        h->ncoarse = n;
-        h->lu = dalloc<double>(h, n * n);
-        h->perm = dalloc<int32_t>(h, n);
+        H.ncoarse = n;
+        H.lu = dalloc<double>(h, n * n);
+        H.perm = dalloc<int32_t>(h, n);
         reset_err(h);
-        launch_dense_lu(n, A.rp, A.ci, A.v, h->lu, h->perm, h->derr, h->stream);
+        launch_dense_lu(n, A.rp, A.ci, A.v, H.lu, H.perm, h->derr, h->stream);
         read_err(h);
         if (h->herr[4]) throw_err(h, MGR_E_SINGULAR_BLOCK, "AMG: coarsest matrix is singular");
         return;
@@ -337,18 +357,33 @@ void alloc_work(mgr_handle *h) {
             lv.t = dalloc<double>(h, lv.n);
         }
     }
-    for (auto &lv : h->amg) {
-        if (mixed) {
-            lv.rf = dalloc<float>(h, lv.n);
-            lv.xf = dalloc<float>(h, lv.n);
-            lv.x2f = dalloc<float>(h, lv.n);
-            lv.tf = dalloc<float>(h, lv.n);
-        } else {
-            lv.r = dalloc<double>(h, lv.n);
-            lv.x = dalloc<double>(h, lv.n);
-            lv.x2 = dalloc<double>(h, lv.n);
-            lv.t = dalloc<double>(h, lv.n);
+    auto amg_work = [&](AmgHier &H) {
+        for (auto &lv : H.lev) {
+            if (mixed) {
+                lv.rf = dalloc<float>(h, lv.n);
+                lv.xf = dalloc<float>(h, lv.n);
+                lv.x2f = dalloc<float>(h, lv.n);
+                lv.tf = dalloc<float>(h, lv.n);
+            } else {
+                lv.r = dalloc<double>(h, lv.n);
+                lv.x = dalloc<double>(h, lv.n);
+                lv.x2 = dalloc<double>(h, lv.n);
+                lv.t = dalloc<double>(h, lv.n);
+            }
         }
+    };
+    amg_work(h->cg);
+    for (auto &lv : h->lev)
+        if (lv.ff) amg_work(*lv.ff);
+}
+
+void amg_to_mixed(mgr_handle *h, AmgHier &H) {
+    for (size_t k = 0; k + 1 < H.lev.size(); ++k) {
+        AmgLevel &lv = H.lev[k];
+        lv.A.vf = to_f32(h, lv.A.v, lv.A.nnz);
+        lv.P.vf = to_f32(h, lv.P.v, lv.P.nnz);
+        lv.PT.vf = to_f32(h, lv.PT.v, lv.PT.nnz);
+        lv.l1f = to_f32(h, lv.l1, lv.n);
     }
 }
 
@@ -360,14 +395,9 @@ void to_mixed(mgr_handle *h) {
         lv.P.vf = to_f32(h, lv.P.v, lv.P.nnz);
         lv.R.vf = to_f32(h, lv.R.v, lv.R.nnz);
         lv.dinvf = to_f32(h, lv.dinv, lv.nF);
+        if (lv.ff) amg_to_mixed(h, *lv.ff);
     }
-    for (size_t k = 0; k + 1 < h->amg.size(); ++k) {
-        AmgLevel &lv = h->amg[k];
-        lv.A.vf = to_f32(h, lv.A.v, lv.A.nnz);
-        lv.P.vf = to_f32(h, lv.P.v, lv.P.nnz);
-        lv.PT.vf = to_f32(h, lv.PT.v, lv.PT.nnz);
-        lv.l1f = to_f32(h, lv.l1, lv.n);
-    }
+    amg_to_mixed(h, h->cg);
 }
 
 // ---------------- V-cycle ----------------
@@ -434,17 +464,17 @@ void fine_op(mgr_handle *h, int mode, const T *x, const T *r, T *y) {
 }
 
 template <typename T>
-void amg_cycle(mgr_handle *h, int k, const T *r, T *x) {
-    AmgLevel &lv = h->amg[k];
+void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x) {
+    AmgLevel &lv = H.lev[k];
     hipStream_t s = h->stream;
     const int64_t n = lv.n;
-    if (k == (int)h->amg.size() - 1) {
-        launch_lu_solve<T>(n, h->lu, h->perm, r, x, s);
+    if (k == (int)H.lev.size() - 1) {
+        launch_lu_solve<T>(n, H.lu, H.perm, r, x, s);
         return;
     }
     const T *Av = P_<T>::v(lv.A);
     const T *l1 = P_<T>::l1(lv);
-    const int pre = h->o.amg_pre, post = h->o.amg_post;
+    const int pre = H.pre, post = H.post;
     // ping-pong buffers arranged so that the last sweep writes x
     const int swaps = (pre > 0 ? pre - 1 : 0) + post;
     T *cur = (swaps % 2 == 0) ? x : P_<T>::x2(lv);
@@ -460,9 +490,9 @@ void amg_cycle(mgr_handle *h, int k, const T *r, T *x) {
     if (pre == 0) P_<T>::fill(cur, n, s);
     T *t = P_<T>::t(lv);
     launch_csr<T>(1, lv.A, Av, cur, r, nullptr, t, s);
-    AmgLevel &nx = h->amg[k + 1];
+    AmgLevel &nx = H.lev[k + 1];
     launch_csr<T>(0, lv.PT, P_<T>::v(lv.PT), t, nullptr, nullptr, P_<T>::r(nx), s);
-    amg_cycle<T>(h, k + 1, P_<T>::r(nx), P_<T>::x(nx));
+    amg_cycle<T>(h, H, k + 1, P_<T>::r(nx), P_<T>::x(nx));
     launch_csr<T>(2, lv.P, P_<T>::v(lv.P), P_<T>::x(nx), nullptr, nullptr, cur, s);
     for (int it = 0; it < post; ++it) {
         launch_csr<T>(3, lv.A, Av, cur, r, l1, oth, s);
@@ -473,7 +503,7 @@ void amg_cycle(mgr_handle *h, int k, const T *r, T *x) {
 template <typename T>
 void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
     if (l == h->L) {
-        amg_cycle<T>(h, 0, r, e);
+        amg_cycle<T>(h, h->cg, 0, r, e);
         return;
     }
     MgrLevel &lv = h->lev[l];
@@ -482,12 +512,26 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
     const T *dinv = P_<T>::dinv(lv);
     T *t = P_<T>::t(lv);
     bool have = false;
+    // (1) global relaxation with the cell blocks (level 0)
     if (l == 0 && h->o.global_relax) {
         launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), r, e, s);
         have = true;
     }
+    // (2) F-relaxation: Jacobi with diag(A_FF), or one AMG V-cycle on A_FF
     for (int sw = 0; sw < h->o.f_sweeps; ++sw) {
-        if (!have) {
+        if (lv.ff) {
+            AmgLevel &f0 = lv.ff->lev[0];
+            T *rF = P_<T>::r(f0), *dF = P_<T>::x(f0);
+            if (!have) {
+                launch_gather<T>(lv.nF, lv.flist, r, rF, s);
+                P_<T>::fill(e, lv.n, s);
+                have = true;
+            } else {
+                launch_csr_rows_residual<T>(lv.A, Av, lv.nF, lv.flist, e, r, rF, s);
+            }
+            amg_cycle<T>(h, *lv.ff, 0, rF, dF);
+            launch_scatter_add<T>(lv.nF, lv.flist, dF, e, s);
+        } else if (!have) {
             launch_frelax_first<T>(lv.n, lv.fmap, dinv, r, e, s);
             have = true;
         } else if (lv.aff_diag) {
@@ -498,6 +542,7 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
         }
     }
     if (!have) P_<T>::fill(e, lv.n, s);
+    // (3) coarse-grid correction e += P M_c^{-1} R (r - A e)
     if (l == 0) fine_op<T>(h, 1, e, r, t);
     else launch_csr<T>(1, lv.A, Av, e, r, nullptr, t, s);
     T *rc, *ec;
@@ -505,8 +550,8 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
         rc = P_<T>::r(h->lev[l + 1]);
         ec = P_<T>::e(h->lev[l + 1]);
     } else {
-        rc = P_<T>::r(h->amg[0]);
-        ec = P_<T>::x(h->amg[0]);
+        rc = P_<T>::r(h->cg.lev[0]);
+        ec = P_<T>::x(h->cg.lev[0]);
     }
     launch_csr<T>(0, lv.R, P_<T>::v(lv.R), t, nullptr, nullptr, rc, s);
     mgr_cycle<T>(h, l + 1, rc, ec);
@@ -515,8 +560,8 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
 
 void apply_prec(mgr_handle *h, const double *v, double *z) {
     if (h->o.precision == 1) {
-        float *rf = h->L > 0 ? h->lev[0].rf : h->amg[0].rf;
-        float *ef = h->L > 0 ? h->lev[0].ef : h->amg[0].xf;
+        float *rf = h->L > 0 ? h->lev[0].rf : h->cg.lev[0].rf;
+        float *ef = h->L > 0 ? h->lev[0].ef : h->cg.lev[0].xf;
         launch_cast_f64_f32(v, rf, h->n, h->stream);
         mgr_cycle<float>(h, 0, rf, ef);
         launch_cast_f32_f64(ef, z, h->n, h->stream);
@@ -628,7 +673,7 @@ void fill_stats(mgr_handle *h, mgr_stats *st) {
             st->level_nnz[k] = lv.A.nnz;
             k++;
         }
-    for (auto &lv : h->amg)
+    for (auto &lv : h->cg.lev)
         if (k < 64) {
             st->level_n[k] = lv.A.nrows;
             st->level_nnz[k] = lv.A.nnz;
@@ -659,6 +704,9 @@ int check_options(const mgr_options *o, std::string &why) {
     else if (o->amg_max_levels < 1 || o->amg_max_levels > 32) why = "amg_max_levels must be in [1, 32]";
     else if (o->amg_coarse_max < 1) why = "amg_coarse_max must be >= 1";
     else if (o->dense_max < 1 || o->dense_max > 4096) why = "dense_max must be in [1, 4096]";
+    else if (o->frelax_amg_mask < 0) why = "frelax_amg_mask must be >= 0";
+    else if (o->frelax_amg_pre < 0 || o->frelax_amg_pre > 8 || o->frelax_amg_post < 0 || o->frelax_amg_post > 8)
+        why = "frelax_amg_pre/post in [0, 8]";
     else return MGR_OK;
     return MGR_E_INVALID;
 }
@@ -750,17 +798,21 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
             build_mgr_level(h, l, An, lab, glob);
             Acur = An;
         }
-        build_amg(h, Acur);
+        build_amg(h, h->cg, Acur, opts->amg_pre, opts->amg_post);
+        auto amg_lanes = [](AmgHier &H) {
+            for (auto &lv : H.lev) {
+                lv.A.lanes = choose_lanes(lv.A);
+                lv.P.lanes = choose_lanes(lv.P);
+                lv.PT.lanes = choose_lanes(lv.PT);
+            }
+        };
         for (auto &lv : h->lev) {
             lv.A.lanes = choose_lanes(lv.A);
             lv.P.lanes = choose_lanes(lv.P);
             lv.R.lanes = choose_lanes(lv.R);
+            if (lv.ff) amg_lanes(*lv.ff);
         }
-        for (auto &lv : h->amg) {
-            lv.A.lanes = choose_lanes(lv.A);
-            lv.P.lanes = choose_lanes(lv.P);
-            lv.PT.lanes = choose_lanes(lv.PT);
-        }
+        amg_lanes(h->cg);
         if (h->o.precision == 1) to_mixed(h);
         alloc_work(h);
         const int m = h->m;
@@ -818,6 +870,9 @@ void mgr_default_options(mgr_options *o) {
     o->pmis_seed = 0;
     o->transpose = 0;
     o->use_x0 = 0;
+    o->frelax_amg_mask = 0;
+    o->frelax_amg_pre = 1;
+    o->frelax_amg_post = 1;
 }
 
 int mgr_setup(const mgr_csr *A, int block_size, const int32_t *cf_labels, const mgr_options *opts,
@@ -903,24 +958,38 @@ const char *mgr_last_error(const mgr_handle *h) { return h ? h->err.c_str() : g_
 int mgr_num_levels(mgr_handle *h, int *nm, int *na) {
     if (!h) return MGR_E_INVALID;
     if (nm) *nm = h->L;
-    if (na) *na = (int)h->amg.size();
+    if (na) *na = (int)h->cg.lev.size();
     return MGR_OK;
+}
+
+// the AMG hierarchy a query refers to: the F-relaxation AMG of MGR level
+// (level >> 8) for the F-block kinds (level becomes its low byte), else the coarse grid
+static AmgHier *query_hier(mgr_handle *h, bool ff_kind, int &level) {
+    if (!ff_kind) return &h->cg;
+    const int l = level >> 8;
+    level &= 0xff;
+    if (l < 0 || l >= h->L || !h->lev[l].ff) return nullptr;
+    return h->lev[l].ff.get();
 }
 
 int mgr_get_matrix(mgr_handle *h, int kind, int level, int64_t *nrows, int64_t *ncols, int64_t *nnz,
                    int32_t *row_ptr, int32_t *col_idx, double *values) {
     if (!h) return MGR_E_INVALID;
     const DCsr *M = nullptr;
-    const int na = (int)h->amg.size();
     if (kind >= 0 && kind <= 2) {
         if (level < 0 || level >= h->L) return MGR_E_INVALID;
         M = kind == 0 ? &h->lev[level].A : kind == 1 ? &h->lev[level].P : &h->lev[level].R;
-    } else if (kind == 3) {
-        if (level < 0 || level >= na) return MGR_E_INVALID;
-        M = &h->amg[level].A;
-    } else if (kind == 4 || kind == 5) {
-        if (level < 0 || level >= na - 1) return MGR_E_INVALID;
-        M = kind == 4 ? &h->amg[level].P : &h->amg[level].S;
+    } else if (kind >= 3 && kind <= 7) {
+        AmgHier *H = query_hier(h, kind >= 6, level);
+        if (!H) return MGR_E_INVALID;
+        const int na = (int)H->lev.size();
+        if (kind == 3 || kind == 6) {
+            if (level < 0 || level >= na) return MGR_E_INVALID;
+            M = &H->lev[level].A;
+        } else {
+            if (level < 0 || level >= na - 1) return MGR_E_INVALID;
+            M = (kind == 4 || kind == 7) ? &H->lev[level].P : &H->lev[level].S;
+        }
     } else {
         return MGR_E_INVALID;
     }
@@ -941,20 +1010,28 @@ int mgr_get_matrix(mgr_handle *h, int kind, int level, int64_t *nrows, int64_t *
 
 int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len) {
     if (!h || !len) return MGR_E_INVALID;
-    const int na = (int)h->amg.size();
     const void *src = nullptr;
     size_t esz = 8;
     int64_t n = -1;
-    switch (kind) {
-    case 0: n = h->binv ? h->ncell * h->bs * h->bs : 0; src = h->binv; break;
-    case 1: if (level >= 0 && level < h->L) { n = h->lev[level].nF; src = h->lev[level].dinv; } break;
-    case 2: if (level >= 0 && level < h->L) { n = h->lev[level].nF; src = h->lev[level].flist; esz = 4; } break;
-    case 3: if (level >= 0 && level < h->L) { n = h->lev[level].nC; src = h->lev[level].clist; esz = 4; } break;
-    case 4: if (level >= 0 && level < na - 1) { n = h->amg[level].n; src = h->amg[level].cf; esz = 4; } break;
-    case 5: if (level >= 0 && level < na - 1) { n = h->amg[level].n; src = h->amg[level].l1; } break;
-    case 6: n = h->ncoarse * h->ncoarse; src = h->lu; break;
-    case 7: n = h->ncoarse; src = h->perm; esz = 4; break;
-    default: break;
+    if (kind >= 0 && kind <= 3) {
+        switch (kind) {
+        case 0: n = h->binv ? h->ncell * h->bs * h->bs : 0; src = h->binv; break;
+        case 1: if (level >= 0 && level < h->L) { n = h->lev[level].nF; src = h->lev[level].dinv; } break;
+        case 2: if (level >= 0 && level < h->L) { n = h->lev[level].nF; src = h->lev[level].flist; esz = 4; } break;
+        case 3: if (level >= 0 && level < h->L) { n = h->lev[level].nC; src = h->lev[level].clist; esz = 4; } break;
+        }
+    } else if (kind >= 4 && kind <= 11) {
+        AmgHier *H = query_hier(h, kind >= 8, level);
+        const int base = kind >= 8 ? kind - 4 : kind;
+        if (H) {
+            const int na = (int)H->lev.size();
+            switch (base) {
+            case 4: if (level >= 0 && level < na - 1) { n = H->lev[level].n; src = H->lev[level].cf; esz = 4; } break;
+            case 5: if (level >= 0 && level < na - 1) { n = H->lev[level].n; src = H->lev[level].l1; } break;
+            case 6: n = H->ncoarse * H->ncoarse; src = H->lu; break;
+            case 7: n = H->ncoarse; src = H->perm; esz = 4; break;
+            }
+        }
     }
     if (n < 0) return MGR_E_INVALID;
     *len = n;

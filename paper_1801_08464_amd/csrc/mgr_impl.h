@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -37,19 +38,6 @@ struct CSell {
     float *vf = nullptr;
 };
 
-struct MgrLevel {
-    int64_t n = 0, nF = 0, nC = 0;
-    DCsr A, P, R;
-    int32_t *flist = nullptr, *clist = nullptr, *fmap = nullptr;
-    int32_t *lab = nullptr, *glob = nullptr;
-    double *dinv = nullptr;
-    float *dinvf = nullptr;
-    bool aff_diag = false;  // A_FF diagonal: the F-relaxation may update in place
-    // V-cycle work vectors
-    double *e = nullptr, *t = nullptr, *r = nullptr;
-    float *ef = nullptr, *tf = nullptr, *rf = nullptr;
-};
-
 struct AmgLevel {
     int64_t n = 0, nc = 0;
     DCsr A, P, PT, S;
@@ -58,6 +46,29 @@ struct AmgLevel {
     float *l1f = nullptr;
     double *r = nullptr, *x = nullptr, *x2 = nullptr, *t = nullptr;
     float *rf = nullptr, *xf = nullptr, *x2f = nullptr, *tf = nullptr;
+};
+
+// one classical AMG hierarchy: the coarse-grid solver, or the F-block solver of an MGR level
+struct AmgHier {
+    std::vector<AmgLevel> lev;
+    int64_t ncoarse = 0;
+    double *lu = nullptr;
+    int32_t *perm = nullptr;
+    int pre = 2, post = 2;
+};
+
+struct MgrLevel {
+    int64_t n = 0, nF = 0, nC = 0;
+    DCsr A, P, R;
+    int32_t *flist = nullptr, *clist = nullptr, *fmap = nullptr;
+    int32_t *lab = nullptr, *glob = nullptr;
+    double *dinv = nullptr;
+    float *dinvf = nullptr;
+    bool aff_diag = false;  // A_FF diagonal: the F-relaxation may update in place
+    std::shared_ptr<AmgHier> ff;  // AMG V-cycle on A_FF as the F-relaxation (else Jacobi)
+    // V-cycle work vectors
+    double *e = nullptr, *t = nullptr, *r = nullptr;
+    float *ef = nullptr, *tf = nullptr, *rf = nullptr;
 };
 
 }  // namespace mgr
@@ -76,11 +87,7 @@ struct mgr_handle {
     double *binv = nullptr;  // 9 planes of ncell (bs = 3) or 1 plane (bs = 1)
     float *binvf = nullptr;
     std::vector<mgr::MgrLevel> lev;
-    std::vector<mgr::AmgLevel> amg;
-    int64_t ncoarse = 0;
-    double *lu = nullptr;
-    int32_t *perm = nullptr;
-    double *lu_b = nullptr, *lu_x = nullptr;
+    mgr::AmgHier cg;  // coarse-grid AMG on the last reduction level
 
     // Krylov workspace
     int m = 30;
@@ -147,6 +154,11 @@ void launch_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, const in
                    const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Rrp, int32_t *Rci,
                    double *Rv, hipStream_t s);
 void launch_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst, hipStream_t s);
+// A_FF: rows flist, columns with fmap >= 0 renumbered by fmap
+void launch_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
+                     int32_t *cnt, hipStream_t s);
+void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
+                    const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s);
 // SpGEMM C = A B, canonical ascending-k summation.  pass 0 counts into cnt, pass 1 fills.
 int spgemm_max_row();
 void launch_spgemm(int pass, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,
@@ -198,6 +210,11 @@ void launch_frelax_inplace(const DCsr &A, const T *vals, int64_t nF, const int32
                            const T *r, T *e, hipStream_t s);
 template <typename T>
 void launch_div(int64_t n, const T *r, const T *d, T *x, hipStream_t s);
+// t[f] = r[idx[f]]  /  e[idx[f]] += d[f]
+template <typename T>
+void launch_gather(int64_t n, const int32_t *idx, const T *src, T *dst, hipStream_t s);
+template <typename T>
+void launch_scatter_add(int64_t n, const int32_t *idx, const T *d, T *e, hipStream_t s);
 template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s);
 

@@ -159,10 +159,11 @@ class MGRSolver:
 
     def get_vector(self, kind, level=0):
         """kind 0 cell-block inverses, 1 dinv_l, 2 F list_l, 3 C list_l, 4 AMG C/F_k,
-        5 AMG l1_k, 6 coarsest LU, 7 coarsest LU permutation."""
+        5 AMG l1_k, 6 coarsest LU, 7 coarsest LU permutation; 8..11 the same as 4..7
+        for the F-relaxation AMG of MGR level l with level = (l << 8) | k."""
         n = C.c_int64()
         self._check(self.lib.mgr_get_vector(self.h, kind, level, None, C.byref(n)))
-        dtype = np.int32 if kind in (2, 3, 4, 7) else np.float64
+        dtype = np.int32 if kind in (2, 3, 4, 7, 8, 11) else np.float64
         out = np.empty(max(n.value, 1), dtype)
         self._check(self.lib.mgr_get_vector(self.h, kind, level, out.ctypes.data, C.byref(n)))
         return out[: n.value]

@@ -43,6 +43,23 @@ def compare_hierarchy(orc, s, **opts):
         lu, perm = o.coarse_lu()
         np.testing.assert_array_equal(g.get_vector(7), perm, err_msg="coarsest LU permutation")
         np.testing.assert_array_equal(g.get_vector(6), lu.ravel(), err_msg="coarsest LU factors")
+        for l in range(nm):
+            nff = o.n_ff_levels(l)
+            for k in range(nff):
+                code = (l << 8) | k
+                ok = o.ff_level(l, k)
+                assert_same_csr(g.get_matrix(6, code), ok["A"], f"F-block AMG A_{k} of level {l}")
+                if k < nff - 1:
+                    assert_same_csr(g.get_matrix(7, code), ok["P"], f"F-block AMG P_{k} of level {l}")
+                    np.testing.assert_array_equal(g.get_vector(8, code), ok["cf"])
+                    np.testing.assert_array_equal(g.get_vector(9, code), ok["l1"])
+            if nff:
+                flu, fperm = o.ff_coarse_lu(l)
+                np.testing.assert_array_equal(g.get_vector(11, l << 8), fperm)
+                np.testing.assert_array_equal(g.get_vector(10, l << 8), flu.ravel())
+            else:
+                with pytest.raises(Exception):
+                    g.get_matrix(6, l << 8)
     finally:
         g.close()
         o.close()
@@ -56,7 +73,9 @@ def test_hierarchy_bitwise(orc, case):
 
 
 @pytest.mark.parametrize("opts", [dict(rp_type=1), dict(rp_type=2), dict(global_relax=0),
-                                  dict(amg_theta=0.5, pmis_seed=12345), dict(amg_coarse_max=10)])
+                                  dict(amg_theta=0.5, pmis_seed=12345), dict(amg_coarse_max=10),
+                                  dict(frelax_amg_mask=2), dict(frelax_amg_mask=2, amg_coarse_max=20,
+                                                                frelax_amg_pre=2, frelax_amg_post=0)])
 def test_hierarchy_bitwise_options(orc, opts):
     s = small_system((19, 17), seed=6)
     print(f"[setup parity] options {opts}", flush=True)

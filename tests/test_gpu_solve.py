@@ -85,11 +85,14 @@ def test_residual_history_monotone():
 
 @pytest.mark.parametrize("opts", [dict(rp_type=1), dict(rp_type=2), dict(global_relax=0), dict(f_sweeps=0),
                                   dict(f_sweeps=2), dict(amg_pre=1, amg_post=3), dict(amg_pre=0, amg_post=1),
-                                  dict(restart=1, max_iter=2000), dict(restart=64)])
+                                  dict(restart=1, max_iter=2000), dict(restart=64), dict(frelax_amg_mask=2),
+                                  dict(frelax_amg_mask=2, f_sweeps=2, global_relax=0),
+                                  dict(frelax_amg_mask=3, precision="mixed")])
 def test_option_variants_match_oracle(orc, opts):
     s = small_system((19, 17), seed=6)
     A = oracle_csr(orc, s)
-    ro = orc.Oracle(A, s.labels, **opts).solve(s.b, 1e-8)
+    oopts = {k: (1 if v == "mixed" else v) for k, v in opts.items()}
+    ro = orc.Oracle(A, s.labels, **oopts).solve(s.b, 1e-8)
     g = gpu_solver(s, **opts)
     x, info = g.solve(s.b, 1e-8)
     assert info.status == ro.status
@@ -162,3 +165,17 @@ def test_status_codes_through_the_abi():
     x, info = g.solve(b, 1e-8)
     assert info.status == B.E_BREAKDOWN
     g.close()
+
+
+def test_amg_frelaxation_solve_matched_iterations(orc):
+    s = small_system((20, 20, 20), seed=4, sigma=2.0, frac=0.3, region="ball")
+    A = oracle_csr(orc, s)
+    ro = orc.Oracle(A, s.labels, frelax_amg_mask=2).solve(s.b, 1e-8)
+    g = gpu_solver(s, frelax_amg_mask=2)
+    x, info = g.solve(s.b, 1e-8)
+    assert info.status == 0 and abs(info.iterations - ro.iterations) <= 1
+    g.close()
+    gm = gpu_solver(s, frelax_amg_mask=2, max_iter=ro.iterations)
+    xm, _ = gm.solve(s.b, 0.0)
+    assert np.linalg.norm(xm.cpu().numpy() - ro.x) / np.linalg.norm(ro.x) <= 1e-8
+    gm.close()

@@ -157,6 +157,87 @@ def test_vcycle_equals_closed_form_propagator(orc, grid):
     np.testing.assert_allclose(cols, Minv, rtol=1e-9, atol=1e-11 * np.abs(Minv).max())
 
 
+def _amg_operator(levels, pre, post):
+    """Dense M^{-1} of an AMG V(pre, post) cycle (l1-Jacobi, exact LU at the bottom)
+    given per-level dicts of dense A, P and l1."""
+    def minv(k):
+        A = levels[k]["A"]
+        n = A.shape[0]
+        if k == len(levels) - 1:
+            return np.linalg.inv(A)
+        P = levels[k]["P"]
+        Sm = np.eye(n) - np.diag(1.0 / levels[k]["l1"]) @ A
+        E = np.linalg.matrix_power(Sm, post) @ (np.eye(n) - P @ minv(k + 1) @ P.T @ A) @ \
+            np.linalg.matrix_power(Sm, pre)
+        return (np.eye(n) - E) @ np.linalg.inv(A)
+    return minv(0)
+
+
+def test_vcycle_with_amg_frelaxation_equals_closed_form(orc):
+    # level 1 relaxes its F-points with one AMG V(1,1)-cycle on A_FF (the paper's
+    # F-relaxation for its phase-transition runs): M_f = I - Q M_FF^{-1} Q^T A
+    s = make_system((9, 9), 1.5, "disk", 0.4, seed=2)
+    A = orc.as_csr(s.indptr, s.indices, s.data)
+    o = orc.Oracle(A, s.labels, frelax_amg_mask=2, amg_coarse_max=20)
+    assert o.n_ff_levels(1) >= 2 and o.n_ff_levels(0) == 0
+    lv1 = o.mgr_level(1)
+    F = lv1["flist"]
+    Aff = dense(orc, lv1["A"])[np.ix_(F, F)]
+    ffl = [o.ff_level(1, k) for k in range(o.n_ff_levels(1))]
+    np.testing.assert_array_equal(dense(orc, ffl[0]["A"]), Aff)
+    levels = [dict(A=dense(orc, d["A"]), P=dense(orc, d["P"]) if "P" in d else None, l1=d.get("l1")) for d in ffl]
+    Mff = _amg_operator(levels, 1, 1)
+    # replace D_FF^{-1} of level 1 by M_FF^{-1} in the recursive propagator
+    L, nl = o.n_mgr_levels, o.n_amg_levels
+
+    def amg_minv(k):
+        lv = o.amg_level(k)
+        Ak = dense(orc, lv["A"])
+        n = Ak.shape[0]
+        if k == nl - 1:
+            return np.linalg.inv(Ak)
+        P = dense(orc, lv["P"])
+        Sm = np.eye(n) - np.diag(1.0 / lv["l1"]) @ Ak
+        E = Sm @ Sm @ (np.eye(n) - P @ amg_minv(k + 1) @ P.T @ Ak) @ Sm @ Sm
+        return (np.eye(n) - E) @ np.linalg.inv(Ak)
+
+    binv = o.block_inverses().reshape(-1, 3, 3)
+    B = np.zeros((s.n, s.n))
+    for c in range(s.n_cells):
+        B[3 * c:3 * c + 3, 3 * c:3 * c + 3] = binv[c]
+
+    def mgr_minv(l):
+        if l == L:
+            return amg_minv(0)
+        lv = o.mgr_level(l)
+        Al = dense(orc, lv["A"])
+        n = Al.shape[0]
+        Fl = lv["flist"]
+        Q = np.zeros((n, len(Fl)))
+        Q[Fl, np.arange(len(Fl))] = 1
+        Mf = Mff if l == 1 else np.diag(lv["dinv"])
+        E = (np.eye(n) - dense(orc, lv["P"]) @ mgr_minv(l + 1) @ dense(orc, lv["R"]) @ Al) @ \
+            (np.eye(n) - Q @ Mf @ Q.T @ Al)
+        if l == 0:
+            E = E @ (np.eye(n) - B @ Al)
+        return (np.eye(n) - E) @ np.linalg.inv(Al)
+
+    Minv = mgr_minv(0)
+    cols = np.stack([o.vcycle(e) for e in np.eye(s.n)], axis=1)
+    np.testing.assert_allclose(cols, Minv, rtol=1e-9, atol=1e-11 * np.abs(Minv).max())
+
+
+def test_amg_frelaxation_restores_convergence(orc):
+    # sigma = 2 in 3D: one Jacobi sweep on the diffusion-dominated rho block is weak;
+    # one AMG V(1,1)-cycle on it brings the iteration count down
+    s = make_system((24, 24, 24), 2.0, "ball", 0.3, seed=4)
+    A = orc.as_csr(s.indptr, s.indices, s.data)
+    rj = orc.Oracle(A, s.labels).solve(s.b, 1e-8)
+    ra = orc.Oracle(A, s.labels, frelax_amg_mask=2).solve(s.b, 1e-8)
+    assert ra.status == 0 and rj.status == 0
+    assert ra.iterations < 0.7 * rj.iterations, (ra.iterations, rj.iterations)
+
+
 def test_fp32_vcycle_close_to_fp64(orc):
     s = small((8, 8))
     A = orc.as_csr(s.indptr, s.indices, s.data)
@@ -166,3 +247,19 @@ def test_fp32_vcycle_close_to_fp64(orc):
     e64, e32 = o64.vcycle(r), o32.vcycle(r)
     assert np.linalg.norm(e32 - e64) / np.linalg.norm(e64) < 1e-4
     assert not np.array_equal(e32, e64)
+
+
+def test_introspection_of_coarse_and_fblock_hierarchies(orc):
+    s = make_system((9, 9), 1.5, "disk", 0.4, seed=2)
+    A = orc.as_csr(s.indptr, s.indices, s.data)
+    o = orc.Oracle(A, s.labels, frelax_amg_mask=2, amg_coarse_max=20)
+    lu, perm = o.coarse_lu()
+    Ac = dense(orc, o.amg_level(o.n_amg_levels - 1)["A"])
+    L = np.tril(lu, -1) + np.eye(lu.shape[0])
+    np.testing.assert_allclose(L @ np.triu(lu), Ac[perm], rtol=1e-12, atol=1e-12 * np.abs(Ac).max())
+    flu, fperm = o.ff_coarse_lu(1)
+    Af = dense(orc, o.ff_level(1, o.n_ff_levels(1) - 1)["A"])
+    L = np.tril(flu, -1) + np.eye(flu.shape[0])
+    np.testing.assert_allclose(L @ np.triu(flu), Af[fperm], rtol=1e-12, atol=1e-12 * np.abs(Af).max())
+    with pytest.raises(IndexError):
+        o.ff_level(0, 0)
