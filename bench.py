@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--adjoint-config", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch of the fine kernel")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy kernel (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -165,6 +167,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # reads and writes exactly 512 MiB each
+        torch.cuda.synchronize()
+        del src, dst
     t = time.perf_counter()
     s = make_config(args.config)
     log(f"config {args.config}: n={s.n} nnz={s.nnz} generated in {time.perf_counter() - t:.1f}s")

@@ -294,31 +294,35 @@ __global__ void k_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, c
 // k) by walking the ballot mask, starting from 0.0.  Patterns are symbolic.
 constexpr int kSpgChunks = 8;
 
-__device__ inline int wave_min_i32(int v) {
+template <int G>
+__device__ inline int group_min_i32(int v) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = G / 2; off > 0; off >>= 1) {
         int o = __shfl_xor(v, off);
         v = o < v ? o : v;
     }
     return v;
 }
 
-template <bool FILL>
+// G lanes (an aligned group of the wavefront) per output row
+template <bool FILL, int G>
 __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__restrict__ Arp,
                                                 const int32_t *__restrict__ Aci, const double *__restrict__ Av,
                                                 const int32_t *__restrict__ Brp, const int32_t *__restrict__ Bci,
                                                 const double *__restrict__ Bv, int32_t *cnt_or_Crp,
                                                 int32_t *__restrict__ Cci, double *__restrict__ Cv, int *err) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (row >= m) return;  // uniform per wavefront
+    const int glane = threadIdx.x & (G - 1);
+    const int gbase = (threadIdx.x & (kWave - 1)) & ~(G - 1);
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / G) + (threadIdx.x / G);
+    if (row >= m) return;  // uniform per group
     const int a0 = Arp[row];
     const int len = Arp[row + 1] - a0;
-    if (len > kWave * kSpgChunks) {
-        if (lane == 0) atomicOr(err, 1);
+    if (len > G * kSpgChunks) {
+        if (glane == 0) atomicOr(err, 1);
         return;
     }
-    const int nch = (len + kWave - 1) / kWave;
+    const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    const int nch = (len + G - 1) / G;
     int p[kSpgChunks], e[kSpgChunks], hd[kSpgChunks];
     double av[kSpgChunks];
 #pragma unroll
@@ -327,7 +331,7 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
         e[c] = 0;
         hd[c] = INT_MAX;
         av[c] = 0.0;
-        int t = c * kWave + lane;
+        int t = c * G + glane;
         if (c < nch && t < len) {
             int k = Aci[a0 + t];
             if (FILL) av[c] = Av[a0 + t];
@@ -343,7 +347,7 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
 #pragma unroll
         for (int c = 0; c < kSpgChunks; ++c)
             if (c < nch) mn = hd[c] < mn ? hd[c] : mn;
-        mn = wave_min_i32(mn);
+        mn = group_min_i32<G>(mn);
         if (mn == INT_MAX) break;
         if (FILL) {
             double acc = 0.0;
@@ -352,15 +356,15 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
                 if (c < nch) {
                     bool hit = hd[c] == mn;
                     double prod = hit ? av[c] * Bv[p[c]] : 0.0;
-                    unsigned long long mask = __ballot(hit);
+                    unsigned long long mask = (__ballot(hit) >> gbase) & gmask;
                     while (mask) {
                         int l = __builtin_ctzll(mask);
-                        acc = acc + __shfl(prod, l);
+                        acc = acc + __shfl(prod, gbase + l);
                         mask &= mask - 1;
                     }
                 }
             }
-            if (lane == 0) {
+            if (glane == 0) {
                 Cci[out + count] = mn;
                 Cv[out + count] = acc;
             }
@@ -374,7 +378,12 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
             }
         }
     }
-    if (!FILL && lane == 0) cnt_or_Crp[row] = count;
+    if (!FILL && glane == 0) cnt_or_Crp[row] = count;
+}
+
+__global__ void k_row_len_max(int64_t m, const int32_t *rp, int *out) {
+    int64_t i = gtid();
+    if (i < m) atomicMax(out, rp[i + 1] - rp[i]);
 }
 
 // ---------------- stable transpose ----------------
@@ -777,16 +786,31 @@ void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const i
     if (nF > 0) k_ff_fill<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, v, fmap, Frp, Fci, Fv);
 }
 int spgemm_max_row() { return kWave * kSpgChunks; }
-void launch_spgemm(int pass, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,
-                   const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci, double *Cv, int *err,
-                   hipStream_t s) {
+void launch_row_len_max(int64_t m, const int32_t *rp, int *out, hipStream_t s) {
+    if (m > 0) k_row_len_max<<<nblocks(m, BT), BT, 0, s>>>(m, rp, out);
+}
+template <bool FILL, int G>
+static void spgemm_g(int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,
+                     const int32_t *Bci, const double *Bv, int32_t *c, int32_t *Cci, double *Cv, int *err,
+                     hipStream_t s) {
+    k_spgemm<FILL, G><<<nblocks(m, BT / G), BT, 0, s>>>(m, Arp, Aci, Av, Brp, Bci, Bv, c, Cci, Cv, err);
+}
+void launch_spgemm(int pass, int group, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av,
+                   const int32_t *Brp, const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci,
+                   double *Cv, int *err, hipStream_t s) {
     if (m <= 0) return;
-    const int rows_per_block = BT / kWave;
-    unsigned g = nblocks(m, rows_per_block);
-    if (pass == 0)
-        k_spgemm<false><<<g, BT, 0, s>>>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err);
-    else
-        k_spgemm<true><<<g, BT, 0, s>>>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err);
+#define MGR_SPG(G)                                                                                     \
+    do {                                                                                               \
+        if (pass == 0) spgemm_g<false, G>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err, s); \
+        else spgemm_g<true, G>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err, s);            \
+    } while (0)
+    switch (group) {
+    case 8: MGR_SPG(8); break;
+    case 16: MGR_SPG(16); break;
+    case 32: MGR_SPG(32); break;
+    default: MGR_SPG(64); break;
+    }
+#undef MGR_SPG
 }
 void launch_transpose_count(int64_t nrows, const int32_t *rp, const int32_t *ci, int32_t *cnt, hipStream_t s) {
     if (nrows > 0) k_transpose_count<<<nblocks(nrows, BT), BT, 0, s>>>(nrows, rp, ci, cnt);

@@ -11,58 +11,98 @@ namespace {
 
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
-// One wavefront per (slice, component): lane l owns row bs*(64 s + l) + v.
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_csell(int64_t ncell, int bs, int64_t npair, const int32_t *__restrict__ off,
-                                               const int32_t *__restrict__ width, const int32_t *__restrict__ col,
-                                               const T *__restrict__ val, const T *__restrict__ x,
-                                               const T *__restrict__ r, T *__restrict__ y) {
+// Fine-level SpMV on the cell-sliced ELL: one wavefront per 64-cell slice, one
+// thread per cell computing all BS rows of its cell (so each cell's outputs are
+// written together, without partial-line writes).  Each component's slots are
+// read in chunks of 8: every column and value load of a chunk (each a contiguous
+// wavefront segment) is issued before the dependent gathers of x.  Row sums run
+// in ascending column order.
+template <typename T, int MODE, int BS>
+__global__ void __launch_bounds__(256) k_csell(int64_t ncell, int64_t nslice, const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ width,
+                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                    const T *__restrict__ x, const T *__restrict__ r,
+                                                    T *__restrict__ y) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t g = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (g >= npair) return;
-    const int64_t s = g / bs;
-    const int comp = (int)(g - s * bs);
+    const int64_t s = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+    if (s >= nslice) return;
     const int64_t c = s * kWave + lane;
-    const int64_t o = off[g];
-    const int w = width[g];
-    const int32_t *cp = col + o * kWave + lane;
-    const T *vp = val + o * kWave + lane;
-    T acc = 0;
-#pragma unroll 4
-    for (int t = 0; t < w; ++t) {
-        const int j = __builtin_nontemporal_load(cp + (int64_t)t * kWave);
-        const T a = __builtin_nontemporal_load(vp + (int64_t)t * kWave);
-        if (j >= 0) acc = acc + a * x[j];
+    T out[BS];
+#pragma unroll
+    for (int comp = 0; comp < BS; ++comp) {
+        const int64_t g = s * BS + comp;
+        const int64_t o = off[g];
+        const int w = width[g];
+        const int32_t *cp = col + o * kWave + lane;
+        const T *vp = val + o * kWave + lane;
+        T acc = 0;
+        for (int t0 = 0; t0 < w; t0 += 8) {
+            int j[8];
+            T a[8], xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                j[u] = t0 + u < w ? cp[(int64_t)(t0 + u) * kWave] : -1;
+                a[u] = t0 + u < w ? vp[(int64_t)(t0 + u) * kWave] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (j[u] >= 0) acc = acc + a[u] * xv[u];
+        }
+        out[comp] = acc;
     }
     if (c < ncell) {
-        const int64_t i = c * bs + comp;
-        if (MODE == 0) y[i] = acc;
-        else if (MODE == 1) y[i] = r[i] - acc;
-        else y[i] = y[i] + acc;
+#pragma unroll
+        for (int comp = 0; comp < BS; ++comp) {
+            const int64_t i = c * BS + comp;
+            if (MODE == 0) y[i] = out[comp];
+            else if (MODE == 1) y[i] = r[i] - out[comp];
+            else y[i] = y[i] + out[comp];
+        }
     }
 }
 
-// LANES threads per row; MODE 0: y = A x, 1: y = r - A x, 2: y += A x, 3: y = x + (r - A x) / d
-template <typename T, int LANES, int MODE>
-__global__ void __launch_bounds__(256) k_csr(int64_t nrows, const int32_t *__restrict__ rp,
-                                             const int32_t *__restrict__ ci, const T *__restrict__ v,
-                                             const T *__restrict__ x, const T *__restrict__ r,
-                                             const T *__restrict__ d, T *__restrict__ y) {
-    const int64_t gid = gtid();
-    const int64_t row = gid / LANES;
-    const int sub = (int)(gid % LANES);
-    T s = 0;
-    if (row < nrows) {
-        const int a = rp[row], b = rp[row + 1];
-        for (int p = a + sub; p < b; p += LANES) s = s + v[p] * x[ci[p]];
+// CSR "stream" SpMV: a workgroup owns 256 consecutive rows.  Their nonzeros are
+// read as one contiguous, fully coalesced stream; each product v*x is staged in
+// LDS; then thread t sums row rb+t sequentially in ascending column order (the
+// row's entries may span several LDS passes, which run in ascending order).
+// No padding, any row-length mix, and the same summation order per row as a
+// sequential CSR loop.
+constexpr int kStreamRows = 256;
+constexpr int kStreamLds = 4096;
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kStreamRows) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const T *__restrict__ v, const T *__restrict__ x,
+                                                            const T *__restrict__ r, const T *__restrict__ d,
+                                                            T *__restrict__ y) {
+    __shared__ T sh[kStreamLds];
+    const int tid = threadIdx.x;
+    const int64_t rb = (int64_t)blockIdx.x * kStreamRows;
+    const int64_t re = rb + kStreamRows < nrows ? rb + kStreamRows : nrows;
+    const int64_t row = rb + tid;
+    const int p0 = rp[rb], p1 = rp[re];
+    int a = 0, b = 0;
+    if (row < re) {
+        a = rp[row];
+        b = rp[row + 1];
     }
-#pragma unroll
-    for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
-    if (row < nrows && sub == 0) {
-        if (MODE == 0) y[row] = s;
-        else if (MODE == 1) y[row] = r[row] - s;
-        else if (MODE == 2) y[row] = y[row] + s;
-        else y[row] = x[row] + (r[row] - s) / d[row];
+    T acc = 0;
+    for (int base = p0; base < p1; base += kStreamLds) {
+        const int lim = base + kStreamLds < p1 ? base + kStreamLds : p1;
+        for (int p = base + tid; p < lim; p += kStreamRows) sh[p - base] = v[p] * x[ci[p]];
+        __syncthreads();
+        const int lo = a > base ? a : base, hi = b < lim ? b : lim;
+        for (int p = lo; p < hi; ++p) acc = acc + sh[p - base];
+        __syncthreads();
+    }
+    if (row < re) {
+        if (MODE == 0) y[row] = acc;
+        else if (MODE == 1) y[row] = r[row] - acc;
+        else if (MODE == 2) y[row] = y[row] + acc;
+        else y[row] = x[row] + (r[row] - acc) / d[row];
     }
 }
 
@@ -191,36 +231,29 @@ constexpr int BT = 256;
 
 template <typename T>
 void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s) {
-    int64_t npair = A.nslice * A.bs;
-    if (npair <= 0) return;
-    unsigned g = nblocks(npair, BT / kWave);
-    if (mode == 0) k_csell<T, 0><<<g, BT, 0, s>>>(A.ncell, A.bs, npair, A.off, A.width, A.col, vals, x, r, y);
-    else if (mode == 1) k_csell<T, 1><<<g, BT, 0, s>>>(A.ncell, A.bs, npair, A.off, A.width, A.col, vals, x, r, y);
-    else k_csell<T, 2><<<g, BT, 0, s>>>(A.ncell, A.bs, npair, A.off, A.width, A.col, vals, x, r, y);
-}
-
-template <typename T, int LANES>
-static void csr_mode(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y,
-                     hipStream_t s) {
-    unsigned g = nblocks(A.nrows * LANES, BT);
-    switch (mode) {
-    case 0: k_csr<T, LANES, 0><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 1: k_csr<T, LANES, 1><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 2: k_csr<T, LANES, 2><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    default: k_csr<T, LANES, 3><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    }
+    if (A.nslice <= 0) return;
+    const unsigned g = nblocks(A.nslice, BT / kWave);
+#define MGR_CSELL(BS)                                                                                             \
+    do {                                                                                                          \
+        if (mode == 0) k_csell<T, 0, BS><<<g, BT, 0, s>>>(A.ncell, A.nslice, A.off, A.width, A.col, vals, x, r, y); \
+        else if (mode == 1)                                                                                       \
+            k_csell<T, 1, BS><<<g, BT, 0, s>>>(A.ncell, A.nslice, A.off, A.width, A.col, vals, x, r, y);           \
+        else k_csell<T, 2, BS><<<g, BT, 0, s>>>(A.ncell, A.nslice, A.off, A.width, A.col, vals, x, r, y);          \
+    } while (0)
+    if (A.bs == 3) MGR_CSELL(3);
+    else MGR_CSELL(1);
+#undef MGR_CSELL
 }
 
 template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
     if (A.nrows <= 0) return;
-    switch (A.lanes) {
-    case 1: csr_mode<T, 1>(mode, A, vals, x, r, d, y, s); break;
-    case 2: csr_mode<T, 2>(mode, A, vals, x, r, d, y, s); break;
-    case 4: csr_mode<T, 4>(mode, A, vals, x, r, d, y, s); break;
-    case 8: csr_mode<T, 8>(mode, A, vals, x, r, d, y, s); break;
-    case 16: csr_mode<T, 16>(mode, A, vals, x, r, d, y, s); break;
-    default: csr_mode<T, 32>(mode, A, vals, x, r, d, y, s); break;
+    const unsigned g = nblocks(A.nrows, kStreamRows);
+    switch (mode) {
+    case 0: k_csr_stream<T, 0><<<g, kStreamRows, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 1: k_csr_stream<T, 1><<<g, kStreamRows, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 2: k_csr_stream<T, 2><<<g, kStreamRows, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    default: k_csr_stream<T, 3><<<g, kStreamRows, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
     }
 }
 

@@ -5,6 +5,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -106,17 +107,25 @@ DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B) {
     C.nrows = A.nrows;
     C.ncols = B.ncols;
     Tmp<int32_t> cnt(h, A.nrows);
+    // lanes per output row: the smallest group whose 8 chunks hold A's longest row
     reset_err(h);
-    launch_spgemm(0, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6, h->stream);
+    launch_row_len_max(A.nrows, A.rp, h->derr + 1, h->stream);
+    read_err(h);
+    const int maxlen = h->herr[1];
+    if (maxlen > spgemm_max_row())
+        throw_err(h, MGR_E_INVALID,
+                  "SpGEMM: a left-operand row exceeds " + std::to_string(spgemm_max_row()) + " entries");
+    const int group = maxlen <= 64 ? 8 : maxlen <= 128 ? 16 : maxlen <= 256 ? 32 : 64;
+    reset_err(h);
+    launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
+                  h->stream);
     C.rp = dalloc<int32_t>(h, A.nrows + 1);
     C.nnz = scan(h, cnt.p, C.rp, A.nrows);
     read_err(h);
-    if (h->herr[6])
-        throw_err(h, MGR_E_INVALID,
-                  "SpGEMM: a left-operand row exceeds " + std::to_string(spgemm_max_row()) + " entries");
+    if (h->herr[6]) throw_err(h, MGR_E_INVALID, "SpGEMM: row length check failed");
     C.ci = dalloc<int32_t>(h, C.nnz);
     C.v = dalloc<double>(h, C.nnz);
-    launch_spgemm(1, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v, h->derr + 6, h->stream);
+    launch_spgemm(1, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v, h->derr + 6, h->stream);
     return C;
 }
 
@@ -799,17 +808,18 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
             Acur = An;
         }
         build_amg(h, h->cg, Acur, opts->amg_pre, opts->amg_post);
-        auto amg_lanes = [](AmgHier &H) {
+        auto pick = [](DCsr &M) { M.lanes = choose_lanes(M); };
+        auto amg_lanes = [&](AmgHier &H) {
             for (auto &lv : H.lev) {
-                lv.A.lanes = choose_lanes(lv.A);
-                lv.P.lanes = choose_lanes(lv.P);
-                lv.PT.lanes = choose_lanes(lv.PT);
+                pick(lv.A);
+                pick(lv.P);
+                pick(lv.PT);
             }
         };
         for (auto &lv : h->lev) {
-            lv.A.lanes = choose_lanes(lv.A);
-            lv.P.lanes = choose_lanes(lv.P);
-            lv.R.lanes = choose_lanes(lv.R);
+            pick(lv.A);
+            pick(lv.P);
+            pick(lv.R);
             if (lv.ff) amg_lanes(*lv.ff);
         }
         amg_lanes(h->cg);

@@ -20,7 +20,7 @@ struct DCsr {
     int32_t *rp = nullptr, *ci = nullptr;
     double *v = nullptr;
     float *vf = nullptr;
-    int lanes = 1;  // threads per row of the vector SpMV kernel
+    int lanes = 1;  // threads per row of the row-list kernels (F-point residual / relaxation)
 };
 
 // Cell-sliced ELL of the level-0 operator: 64 consecutive cells form a slice;
@@ -160,10 +160,12 @@ void launch_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const 
 void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
                     const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s);
 // SpGEMM C = A B, canonical ascending-k summation.  pass 0 counts into cnt, pass 1 fills.
+// group = lanes per output row (8, 16, 32, 64); rows of A may hold up to group * 8 entries.
 int spgemm_max_row();
-void launch_spgemm(int pass, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,
-                   const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci, double *Cv, int *err,
-                   hipStream_t s);
+void launch_row_len_max(int64_t m, const int32_t *rp, int *out, hipStream_t s);
+void launch_spgemm(int pass, int group, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av,
+                   const int32_t *Brp, const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci,
+                   double *Cv, int *err, hipStream_t s);
 // stable transpose: count (atomics), fill (atomics), then per-row sort by source row
 void launch_transpose_count(int64_t nrows, const int32_t *rp, const int32_t *ci, int32_t *cnt, hipStream_t s);
 void launch_transpose_fill(int64_t nrows, const int32_t *rp, const int32_t *ci, const double *v, int32_t *next,
