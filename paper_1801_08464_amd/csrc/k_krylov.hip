@@ -31,37 +31,99 @@ __device__ inline double block_sum(double v, double *sh) {
     return r;
 }
 
+// Per-block partials of NV+1 running sums (entry NV holds <w, w>): wavefront
+// sums, then one synchronisation and a fixed-order sum over the 4 wavefronts.
+template <int NV>
+__device__ inline void write_partials(const double (&acc)[NV + 1], int nv, double (*sh)[NV + 1], double *part) {
+    const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) {
+        if (i < nv || i == NV) {  // uniform over the block
+            const double v = wave_sum(acc[i]);
+            if (l == 0) sh[wv][i] = v;
+        }
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t <= nv) {
+        const int i = t == nv ? NV : t;
+        double s = sh[0][i];
+#pragma unroll
+        for (int k = 1; k < BT / kWave; ++k) s = s + sh[k][i];
+        part[(int64_t)blockIdx.x * (nv + 1) + t] = s;
+    }
+}
+
+__device__ inline const double2 *vec2(const double *base, int i, int64_t ld) {
+    return reinterpret_cast<const double2 *>(base + (int64_t)i * ld);
+}
+
 // part[b*(nv+1) + i] = sum over this block's elements of w*V_i (i < nv), and w*w at i = nv
 template <int NV>
-__global__ void __launch_bounds__(BT) k_mdot(int64_t n, int nv, const double *__restrict__ V,
-                                             const double *__restrict__ w, double *__restrict__ part,
-                                             const int *guard) {
-    if (guard && *guard == 0) return;
-    __shared__ double sh[BT / kWave];
+__global__ void __launch_bounds__(BT) k_mdot(int64_t n2, int64_t ld, int nv, const double *__restrict__ V,
+                                             const double *__restrict__ w, double *__restrict__ part) {
+    __shared__ double sh[BT / kWave][NV + 1];
     double acc[NV + 1];
 #pragma unroll
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    const double2 *w2 = reinterpret_cast<const double2 *>(w);
     const int64_t stride = (int64_t)gridDim.x * BT;
-    for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < n; q += stride) {
-        const double wq = w[q];
+    for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < n2; q += stride) {
+        const double2 wq = w2[q];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) acc[i] = acc[i] + wq * V[(int64_t)i * n + q];
-        acc[NV] = acc[NV] + wq * wq;
+            if (i < nv) {
+                const double2 vq = vec2(V, i, ld)[q];
+                acc[i] = acc[i] + wq.x * vq.x;
+                acc[i] = acc[i] + wq.y * vq.y;
+            }
+        acc[NV] = acc[NV] + wq.x * wq.x;
+        acc[NV] = acc[NV] + wq.y * wq.y;
     }
-    // fully unrolled so that acc stays in registers; the condition is uniform over the block
+    write_partials<NV>(acc, nv, sh, part);
+}
+
+// w -= sum_i h[i] V_i, then the partials of <w, V_i> and <w, w> for the updated w
+// (the projection of the first Gram-Schmidt pass fused with the dot products of
+// the second: V is read once for both)
+template <int NV>
+__global__ void __launch_bounds__(BT) k_maxpy_dot(int64_t n2, int64_t ld, int nv, const double *__restrict__ V,
+                                                  const double *__restrict__ h, double *__restrict__ w,
+                                                  double *__restrict__ part) {
+    __shared__ double sh[BT / kWave][NV + 1];
+    double hh[NV], acc[NV + 1];
 #pragma unroll
-    for (int i = 0; i <= NV; ++i) {
-        if (i < nv || i == NV) {
-            double s = block_sum(acc[i], sh);
-            if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (nv + 1) + (i == NV ? nv : i)] = s;
-        }
+    for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    double2 *w2 = reinterpret_cast<double2 *>(w);
+    const int64_t stride = (int64_t)gridDim.x * BT;
+    for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < n2; q += stride) {
+        double2 wq = w2[q];
+        double2 vq[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) {
+                vq[i] = vec2(V, i, ld)[q];
+                wq.x = wq.x - hh[i] * vq[i].x;
+                wq.y = wq.y - hh[i] * vq[i].y;
+            }
+        w2[q] = wq;
+#pragma unroll
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) {
+                acc[i] = acc[i] + wq.x * vq[i].x;
+                acc[i] = acc[i] + wq.y * vq[i].y;
+            }
+        acc[NV] = acc[NV] + wq.x * wq.x;
+        acc[NV] = acc[NV] + wq.y * wq.y;
     }
+    write_partials<NV>(acc, nv, sh, part);
 }
 
 // w -= sum_i h[i] V_i ; part[b] = partial of <w, w> after the update
 template <int NV>
-__global__ void __launch_bounds__(BT) k_maxpy_norm(int64_t n, int nv, const double *__restrict__ V,
+__global__ void __launch_bounds__(BT) k_maxpy_norm(int64_t n2, int64_t ld, int nv, const double *__restrict__ V,
                                                    const double *__restrict__ h, double *__restrict__ w,
                                                    double *__restrict__ part, const int *guard) {
     if (guard && *guard == 0) return;
@@ -70,21 +132,27 @@ __global__ void __launch_bounds__(BT) k_maxpy_norm(int64_t n, int nv, const doub
 #pragma unroll
     for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
     double acc = 0.0;
+    double2 *w2 = reinterpret_cast<double2 *>(w);
     const int64_t stride = (int64_t)gridDim.x * BT;
-    for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < n; q += stride) {
-        double wq = w[q];
+    for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < n2; q += stride) {
+        double2 wq = w2[q];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) wq = wq - hh[i] * V[(int64_t)i * n + q];
-        w[q] = wq;
-        acc = acc + wq * wq;
+            if (i < nv) {
+                const double2 vq = vec2(V, i, ld)[q];
+                wq.x = wq.x - hh[i] * vq.x;
+                wq.y = wq.y - hh[i] * vq.y;
+            }
+        w2[q] = wq;
+        acc = acc + wq.x * wq.x;
+        acc = acc + wq.y * wq.y;
     }
-    double s = block_sum(acc, sh);
+    const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 template <int NV>
-__global__ void __launch_bounds__(BT) k_zaxpy(int64_t n, int nv, const double *__restrict__ Z,
+__global__ void __launch_bounds__(BT) k_zaxpy(int64_t n, int64_t ld, int nv, const double *__restrict__ Z,
                                               const double *__restrict__ y, double *__restrict__ x) {
     double yy[NV];
 #pragma unroll
@@ -94,7 +162,7 @@ __global__ void __launch_bounds__(BT) k_zaxpy(int64_t n, int nv, const double *_
         double s = x[q];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) s = s + yy[i] * Z[(int64_t)i * n + q];
+            if (i < nv) s = s + yy[i] * Z[(int64_t)i * ld + q];
         x[q] = s;
     }
 }
@@ -122,39 +190,45 @@ __global__ void k_axpby(int64_t n, double a, const double *__restrict__ x, doubl
 }
 
 // stage 0: h_i = sum of partials (i <= j) -> H(:,j) and hcur; WN0 = <w,w> before the update
-// stage 1: WN = <w,w> after the update; guard = 1 if WN < WN0 / 2 (DGKS test)
-// stage 2: second pass (only when guard): H(:,j) += h_i, hcur = h_i
-// stage 3: WN = <w,w> after the second update
-// One block per reduced value (blockIdx.x = i); each sums its nblk partials with a
-// fixed thread/tree order, so the result does not depend on scheduling.
+// stage 1: after the fused update-and-dot pass: h2_i = <w, V_i>, WN = <w,w>, and
+//          guard = 1 if WN < WN0 / 2 (the DGKS test: a second projection is needed)
+// stage 3: only when guard: WN = <w,w> after the second update, H(:,j) += h2
+// Stages 0 and 1 run one block per reduced value (blockIdx.x = i); every sum runs
+// in a fixed thread/tree order, so the result does not depend on scheduling.
 __global__ void __launch_bounds__(BT) k_arnoldi_fin(int stage, int j, int m, int nblk, const double *__restrict__ part,
                                                     double *__restrict__ dsc, int *guard) {
-    if ((stage == 2 || stage == 3) && *guard == 0) return;
+    if (stage == 3 && *guard == 0) return;
     __shared__ double sh[BT / kWave];
     const int t = threadIdx.x;
     const int i = blockIdx.x;
-    if (stage == 0 || stage == 2) {
-        const int nv = j + 1;
+    const int nv = j + 1;
+    if (stage == 0 || stage == 1) {
         double s = 0.0;
         for (int b = t; b < nblk; b += BT) s += part[(int64_t)b * (nv + 1) + i];
         s = block_sum(s, sh);
         if (t == 0) {
-            if (i < nv) {
-                if (stage == 0) dsc[Dsc::H(i, j, m)] = s;
-                else dsc[Dsc::H(i, j, m)] += s;
-                dsc[Dsc::hcur(i, m)] = s;
-            } else if (stage == 0) {
-                dsc[Dsc::WN0] = s;
+            if (stage == 0) {
+                if (i < nv) {
+                    dsc[Dsc::H(i, j, m)] = s;
+                    dsc[Dsc::hcur(i, m)] = s;
+                } else {
+                    dsc[Dsc::WN0] = s;
+                }
+            } else {
+                if (i < nv) {
+                    dsc[Dsc::h2(i, m)] = s;
+                } else {
+                    dsc[Dsc::WN] = s;
+                    *guard = (s < 0.5 * dsc[Dsc::WN0]) ? 1 : 0;
+                }
             }
         }
     } else {
         double s = 0.0;
         for (int b = t; b < nblk; b += BT) s += part[b];
         s = block_sum(s, sh);
-        if (t == 0) {
-            dsc[Dsc::WN] = s;
-            if (stage == 1) *guard = (s < 0.5 * dsc[Dsc::WN0]) ? 1 : 0;
-        }
+        if (t == 0) dsc[Dsc::WN] = s;
+        if (t < nv) dsc[Dsc::H(t, j, m)] += dsc[Dsc::h2(t, m)];
     }
 }
 
@@ -212,35 +286,51 @@ static unsigned red_grid(int64_t n) {
     return (unsigned)(g > 0 ? g : 1);
 }
 
-void launch_mdot(int64_t n, int nv, const double *V, const double *w, double *part, const int *guard,
-                 hipStream_t s) {
-    unsigned g = red_grid(n);
-    if (nv <= 4) k_mdot<4><<<g, BT, 0, s>>>(n, nv, V, w, part, guard);
-    else if (nv <= 8) k_mdot<8><<<g, BT, 0, s>>>(n, nv, V, w, part, guard);
-    else if (nv <= 16) k_mdot<16><<<g, BT, 0, s>>>(n, nv, V, w, part, guard);
-    else if (nv <= 32) k_mdot<32><<<g, BT, 0, s>>>(n, nv, V, w, part, guard);
-    else k_mdot<kMaxV><<<g, BT, 0, s>>>(n, nv, V, w, part, guard);
+int64_t krylov_ld(int64_t n) { return (n + 63) / 64 * 64; }
+
+#define MGR_NV_DISPATCH(KERNEL, nv, ...)                                          \
+    do {                                                                          \
+        if ((nv) <= 4) KERNEL<4><<<g, BT, 0, s>>>(__VA_ARGS__);                   \
+        else if ((nv) <= 8) KERNEL<8><<<g, BT, 0, s>>>(__VA_ARGS__);              \
+        else if ((nv) <= 16) KERNEL<16><<<g, BT, 0, s>>>(__VA_ARGS__);            \
+        else if ((nv) <= 32) KERNEL<32><<<g, BT, 0, s>>>(__VA_ARGS__);            \
+        else KERNEL<kMaxV><<<g, BT, 0, s>>>(__VA_ARGS__);                         \
+    } while (0)
+
+void launch_mdot(int64_t n, int64_t ld, int nv, const double *V, const double *w, double *part, hipStream_t s) {
+    const int64_t n2 = (n + 1) / 2;
+    const unsigned g = red_grid(n);
+    MGR_NV_DISPATCH(k_mdot, nv, n2, ld, nv, V, w, part);
 }
 
-void launch_maxpy_norm(int64_t n, int nv, const double *V, const double *h, double *w, double *part,
+void launch_maxpy_dot(int64_t n, int64_t ld, int nv, const double *V, const double *h, double *w, double *part,
+                      hipStream_t s) {
+    const int64_t n2 = (n + 1) / 2;
+    const unsigned g = red_grid(n);
+    if (nv <= 4) k_maxpy_dot<4><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
+    else if (nv <= 8) k_maxpy_dot<8><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
+    else if (nv <= 16) k_maxpy_dot<16><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
+    else if (nv <= kFusedMaxV) k_maxpy_dot<kFusedMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
+    else {
+        // too wide to hold the basis chunk in registers: update, then dot
+        k_maxpy_norm<kMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part, nullptr);
+        k_mdot<kMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, w, part);
+    }
+}
+
+void launch_maxpy_norm(int64_t n, int64_t ld, int nv, const double *V, const double *h, double *w, double *part,
                        const int *guard, hipStream_t s) {
-    unsigned g = red_grid(n);
-    if (nv <= 4) k_maxpy_norm<4><<<g, BT, 0, s>>>(n, nv, V, h, w, part, guard);
-    else if (nv <= 8) k_maxpy_norm<8><<<g, BT, 0, s>>>(n, nv, V, h, w, part, guard);
-    else if (nv <= 16) k_maxpy_norm<16><<<g, BT, 0, s>>>(n, nv, V, h, w, part, guard);
-    else if (nv <= 32) k_maxpy_norm<32><<<g, BT, 0, s>>>(n, nv, V, h, w, part, guard);
-    else k_maxpy_norm<kMaxV><<<g, BT, 0, s>>>(n, nv, V, h, w, part, guard);
+    const int64_t n2 = (n + 1) / 2;
+    const unsigned g = red_grid(n);
+    MGR_NV_DISPATCH(k_maxpy_norm, nv, n2, ld, nv, V, h, w, part, guard);
 }
 
-void launch_zaxpy(int64_t n, int nv, const double *Z, const double *y, double *x, hipStream_t s) {
+void launch_zaxpy(int64_t n, int64_t ld, int nv, const double *Z, const double *y, double *x, hipStream_t s) {
     if (nv <= 0) return;
-    unsigned g = red_grid(n);
-    if (nv <= 4) k_zaxpy<4><<<g, BT, 0, s>>>(n, nv, Z, y, x);
-    else if (nv <= 8) k_zaxpy<8><<<g, BT, 0, s>>>(n, nv, Z, y, x);
-    else if (nv <= 16) k_zaxpy<16><<<g, BT, 0, s>>>(n, nv, Z, y, x);
-    else if (nv <= 32) k_zaxpy<32><<<g, BT, 0, s>>>(n, nv, Z, y, x);
-    else k_zaxpy<kMaxV><<<g, BT, 0, s>>>(n, nv, Z, y, x);
+    const unsigned g = red_grid(n);
+    MGR_NV_DISPATCH(k_zaxpy, nv, n, ld, nv, Z, y, x);
 }
+#undef MGR_NV_DISPATCH
 
 void launch_norm_part(int64_t n, const double *a, double *part, hipStream_t s) {
     k_norm_part<<<red_grid(n), BT, 0, s>>>(n, a, part);
@@ -256,7 +346,7 @@ void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hip
 
 void launch_arnoldi_fin(int stage, int j, int m, int nblk, const double *part, double *dsc, int *guard,
                         hipStream_t s) {
-    const unsigned g = (stage == 0 || stage == 2) ? (unsigned)(j + 2) : 1u;
+    const unsigned g = (stage == 0 || stage == 1) ? (unsigned)(j + 2) : 1u;
     k_arnoldi_fin<<<g, BT, 0, s>>>(stage, j, m, nblk, part, dsc, guard);
 }
 

@@ -381,9 +381,26 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
     if (!FILL && glane == 0) cnt_or_Crp[row] = count;
 }
 
-__global__ void k_row_len_max(int64_t m, const int32_t *rp, int *out) {
-    int64_t i = gtid();
-    if (i < m) atomicMax(out, rp[i + 1] - rp[i]);
+// sum and maximum of the lengths of rows list[0..m) (or rows 0..m when list is null);
+// reduced per wavefront first, one integer atomic per wavefront
+__global__ void k_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx) {
+    const int64_t q = gtid();
+    int len = 0;
+    if (q < m) {
+        const int64_t i = list ? list[q] : q;
+        len = rp[i + 1] - rp[i];
+    }
+    int s = len, x = len;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o);
+        const int y = __shfl_xor(x, o);
+        x = y > x ? y : x;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (sum) atomicAdd(sum, s);
+        atomicMax(mx, x);
+    }
 }
 
 // ---------------- stable transpose ----------------
@@ -786,8 +803,8 @@ void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const i
     if (nF > 0) k_ff_fill<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, v, fmap, Frp, Fci, Fv);
 }
 int spgemm_max_row() { return kWave * kSpgChunks; }
-void launch_row_len_max(int64_t m, const int32_t *rp, int *out, hipStream_t s) {
-    if (m > 0) k_row_len_max<<<nblocks(m, BT), BT, 0, s>>>(m, rp, out);
+void launch_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx, hipStream_t s) {
+    if (m > 0) k_row_len_stats<<<nblocks(m, BT), BT, 0, s>>>(m, list, rp, sum, mx);
 }
 template <bool FILL, int G>
 static void spgemm_g(int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,

@@ -63,25 +63,29 @@ __global__ void __launch_bounds__(256) k_csell(int64_t ncell, int64_t nslice, co
     }
 }
 
-// CSR "stream" SpMV: a workgroup owns 256 consecutive rows.  Their nonzeros are
-// read as one contiguous, fully coalesced stream; each product v*x is staged in
-// LDS; then thread t sums row rb+t sequentially in ascending column order (the
-// row's entries may span several LDS passes, which run in ascending order).
-// No padding, any row-length mix, and the same summation order per row as a
-// sequential CSR loop.
-constexpr int kStreamRows = 256;
-constexpr int kStreamLds = 4096;
+// CSR "stream" SpMV: a workgroup owns ROWS consecutive rows.  Their nonzeros are
+// read as one contiguous, coalesced stream in passes of LDSN entries; within a
+// pass each thread issues the column and value loads of 8 entries before their
+// dependent gathers of x, and stages the products v*x in LDS.  Then thread t sums
+// row rb+t sequentially in ascending column order (a row's entries may span
+// several passes, which run in ascending order).  No padding, any row-length mix,
+// and the same summation order per row as a sequential CSR loop.  The matrix is
+// streamed with non-temporal loads so that it does not evict x from the caches.
+template <int ROWS>
+struct StreamCfg {
+    static constexpr int lds = ROWS >= 256 ? 4096 : 32 * ROWS;
+};
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kStreamRows) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
-                                                            const int32_t *__restrict__ ci,
-                                                            const T *__restrict__ v, const T *__restrict__ x,
-                                                            const T *__restrict__ r, const T *__restrict__ d,
-                                                            T *__restrict__ y) {
-    __shared__ T sh[kStreamLds];
+template <typename T, int MODE, int ROWS>
+__global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci, const T *__restrict__ v,
+                                                     const T *__restrict__ x, const T *__restrict__ r,
+                                                     const T *__restrict__ d, T *__restrict__ y) {
+    constexpr int LDSN = StreamCfg<ROWS>::lds;
+    __shared__ T sh[LDSN];
     const int tid = threadIdx.x;
-    const int64_t rb = (int64_t)blockIdx.x * kStreamRows;
-    const int64_t re = rb + kStreamRows < nrows ? rb + kStreamRows : nrows;
+    const int64_t rb = (int64_t)blockIdx.x * ROWS;
+    const int64_t re = rb + ROWS < nrows ? rb + ROWS : nrows;
     const int64_t row = rb + tid;
     const int p0 = rp[rb], p1 = rp[re];
     int a = 0, b = 0;
@@ -90,9 +94,25 @@ __global__ void __launch_bounds__(kStreamRows) k_csr_stream(int64_t nrows, const
         b = rp[row + 1];
     }
     T acc = 0;
-    for (int base = p0; base < p1; base += kStreamLds) {
-        const int lim = base + kStreamLds < p1 ? base + kStreamLds : p1;
-        for (int p = base + tid; p < lim; p += kStreamRows) sh[p - base] = v[p] * x[ci[p]];
+    for (int base = p0; base < p1; base += LDSN) {
+        const int lim = base + LDSN < p1 ? base + LDSN : p1;
+        for (int c0 = base; c0 < lim; c0 += 8 * ROWS) {
+            int j[8];
+            T a8[8], x8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = c0 + u * ROWS + tid;
+                j[u] = p < lim ? __builtin_nontemporal_load(ci + p) : -1;
+                a8[u] = p < lim ? __builtin_nontemporal_load(v + p) : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x8[u] = j[u] >= 0 ? x[j[u]] : (T)0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = c0 + u * ROWS + tid;
+                if (p < lim) sh[p - base] = a8[u] * x8[u];
+            }
+        }
         __syncthreads();
         const int lo = a > base ? a : base, hi = b < lim ? b : lim;
         for (int p = lo; p < hi; ++p) acc = acc + sh[p - base];
@@ -245,23 +265,32 @@ void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *
 #undef MGR_CSELL
 }
 
-template <typename T>
-void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
-    if (A.nrows <= 0) return;
-    const unsigned g = nblocks(A.nrows, kStreamRows);
+template <typename T, int ROWS>
+static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y,
+                     hipStream_t s) {
+    const unsigned g = nblocks(A.nrows, ROWS);
     switch (mode) {
-    case 0: k_csr_stream<T, 0><<<g, kStreamRows, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 1: k_csr_stream<T, 1><<<g, kStreamRows, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 2: k_csr_stream<T, 2><<<g, kStreamRows, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    default: k_csr_stream<T, 3><<<g, kStreamRows, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 0: k_csr_stream<T, 0, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 1: k_csr_stream<T, 1, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 2: k_csr_stream<T, 2, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    default: k_csr_stream<T, 3, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
     }
 }
 
+// 256-row workgroups when they fill the chip several times over, else one
+// wavefront per workgroup so that small coarse levels still spread over the CUs
 template <typename T>
-void launch_csr_rows_residual(const DCsr &A, const T *vals, int64_t nrows, const int32_t *rows, const T *e,
-                              const T *r, T *t, hipStream_t s) {
+void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
+    if (A.nrows <= 0) return;
+    if (A.nrows >= (int64_t)256 * 2048) csr_rows<T, 256>(mode, A, vals, x, r, d, y, s);
+    else csr_rows<T, 64>(mode, A, vals, x, r, d, y, s);
+}
+
+template <typename T>
+void launch_csr_rows_residual(const DCsr &A, int lanes, const T *vals, int64_t nrows, const int32_t *rows,
+                              const T *e, const T *r, T *t, hipStream_t s) {
     if (nrows <= 0) return;
-    int L = A.lanes;
+    const int L = lanes;
     unsigned g = nblocks(nrows * L, BT);
     switch (L) {
     case 1: k_csr_rows_res<T, 1><<<g, BT, 0, s>>>(nrows, rows, A.rp, A.ci, vals, e, r, t); break;
@@ -274,10 +303,10 @@ void launch_csr_rows_residual(const DCsr &A, const T *vals, int64_t nrows, const
 }
 
 template <typename T>
-void launch_frelax_inplace(const DCsr &A, const T *vals, int64_t nF, const int32_t *flist, const T *dinv,
-                           const T *r, T *e, hipStream_t s) {
+void launch_frelax_inplace(const DCsr &A, int lanes, const T *vals, int64_t nF, const int32_t *flist,
+                           const T *dinv, const T *r, T *e, hipStream_t s) {
     if (nF <= 0) return;
-    int L = A.lanes;
+    const int L = lanes;
     unsigned g = nblocks(nF * L, BT);
     switch (L) {
     case 1: k_frelax_inplace<T, 1><<<g, BT, 0, s>>>(nF, flist, A.rp, A.ci, vals, dinv, r, e); break;
@@ -329,9 +358,9 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
 #define MGR_INSTANTIATE(T)                                                                                      \
     template void launch_csell<T>(int, const CSell &, const T *, const T *, const T *, T *, hipStream_t);       \
     template void launch_csr<T>(int, const DCsr &, const T *, const T *, const T *, const T *, T *, hipStream_t); \
-    template void launch_csr_rows_residual<T>(const DCsr &, const T *, int64_t, const int32_t *, const T *,      \
+    template void launch_csr_rows_residual<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *, \
                                               const T *, T *, hipStream_t);                                     \
-    template void launch_frelax_inplace<T>(const DCsr &, const T *, int64_t, const int32_t *, const T *,        \
+    template void launch_frelax_inplace<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *,   \
                                            const T *, T *, hipStream_t);                                        \
     template void launch_block_apply<T>(int64_t, int, const T *, const T *, T *, hipStream_t);                  \
     template void launch_frelax_first<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);     \

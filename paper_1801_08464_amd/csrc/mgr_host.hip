@@ -109,7 +109,7 @@ DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B) {
     Tmp<int32_t> cnt(h, A.nrows);
     // lanes per output row: the smallest group whose 8 chunks hold A's longest row
     reset_err(h);
-    launch_row_len_max(A.nrows, A.rp, h->derr + 1, h->stream);
+    launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
     read_err(h);
     const int maxlen = h->herr[1];
     if (maxlen > spgemm_max_row())
@@ -196,6 +196,16 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
         throw_err(h, MGR_E_ZERO_FDIAG, msg);
     }
     lv.aff_diag = h->herr[5] == 0;
+    // lanes of the F-row kernels from the mean length of the F rows
+    if (lv.nF > 0) {
+        reset_err(h);
+        launch_row_len_stats(lv.nF, lv.flist, A.rp, h->derr + 1, h->derr + 2, h->stream);
+        read_err(h);
+        DCsr rows;
+        rows.nrows = lv.nF;
+        rows.nnz = h->herr[1];
+        lv.flanes = choose_lanes(rows);
+    }
     // optional F-relaxation by one AMG V-cycle on A_FF
     if (((h->o.frelax_amg_mask >> l) & 1) && lv.nF > 0) {
         Tmp<int32_t> cnt(h, lv.nF);
@@ -536,7 +546,7 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
                 P_<T>::fill(e, lv.n, s);
                 have = true;
             } else {
-                launch_csr_rows_residual<T>(lv.A, Av, lv.nF, lv.flist, e, r, rF, s);
+                launch_csr_rows_residual<T>(lv.A, lv.flanes, Av, lv.nF, lv.flist, e, r, rF, s);
             }
             amg_cycle<T>(h, *lv.ff, 0, rF, dF);
             launch_scatter_add<T>(lv.nF, lv.flist, dF, e, s);
@@ -544,9 +554,9 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
             launch_frelax_first<T>(lv.n, lv.fmap, dinv, r, e, s);
             have = true;
         } else if (lv.aff_diag) {
-            launch_frelax_inplace<T>(lv.A, Av, lv.nF, lv.flist, dinv, r, e, s);
+            launch_frelax_inplace<T>(lv.A, lv.flanes, Av, lv.nF, lv.flist, dinv, r, e, s);
         } else {
-            launch_csr_rows_residual<T>(lv.A, Av, lv.nF, lv.flist, e, r, t, s);
+            launch_csr_rows_residual<T>(lv.A, lv.flanes, Av, lv.nF, lv.flist, e, r, t, s);
             launch_frelax_scatter<T>(lv.nF, lv.flist, dinv, t, e, s);
         }
     }
@@ -588,10 +598,12 @@ double dev_norm(mgr_handle *h, const double *a, double *out) {
 int gmres(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) {
     const int64_t n = h->n;
     const int m = h->m;
+    const int64_t ld = h->ld;
     hipStream_t s = h->stream;
     double *dsc = h->dsc;
     const int nblk = red_blocks(n);
     int *guard = h->derr + 7;
+    if (ld > n) launch_fill_f64(h->w + n, 0.0, ld - n, s);  // a breakdown may have left NaN there
     int its = 0;
     double rel = 0.0;
     if (st) st->res_history_len = 0;
@@ -630,17 +642,17 @@ int gmres(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) 
         int k = 0;
         bool broke = false;
         for (int j = 0; j < m; ++j) {
-            double *vj = h->V + (int64_t)j * n;
-            double *zj = h->Z + (int64_t)j * n;
+            double *vj = h->V + (int64_t)j * ld;
+            double *zj = h->Z + (int64_t)j * ld;
             apply_prec(h, vj, zj);
             fine_op<double>(h, 0, zj, nullptr, h->w);
-            launch_mdot(n, j + 1, h->V, h->w, h->part, nullptr, s);
+            // classical Gram-Schmidt; the DGKS second projection runs only when
+            // the first one cancelled more than half of ||w||^2 (guard on device)
+            launch_mdot(n, ld, j + 1, h->V, h->w, h->part, s);
             launch_arnoldi_fin(0, j, m, nblk, h->part, dsc, guard, s);
-            launch_maxpy_norm(n, j + 1, h->V, dsc + Dsc::hcur(0, m), h->w, h->part, nullptr, s);
+            launch_maxpy_dot(n, ld, j + 1, h->V, dsc + Dsc::hcur(0, m), h->w, h->part, s);
             launch_arnoldi_fin(1, j, m, nblk, h->part, dsc, guard, s);
-            launch_mdot(n, j + 1, h->V, h->w, h->part, guard, s);
-            launch_arnoldi_fin(2, j, m, nblk, h->part, dsc, guard, s);
-            launch_maxpy_norm(n, j + 1, h->V, dsc + Dsc::hcur(0, m), h->w, h->part, guard, s);
+            launch_maxpy_norm(n, ld, j + 1, h->V, dsc + Dsc::h2(0, m), h->w, h->part, guard, s);
             launch_arnoldi_fin(3, j, m, nblk, h->part, dsc, guard, s);
             launch_givens(j, m, dsc, s);
             HIPCHK(hipMemcpyAsync(h->hsc, dsc + Dsc::GABS, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -655,14 +667,14 @@ int gmres(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) 
                 break;
             }
             if (gabs <= tol * bnorm || hn == 0.0 || its >= h->o.max_iter) break;
-            launch_scale_dev(n, h->w, dsc + Dsc::HN, 1, h->V + (int64_t)(j + 1) * n, s);
+            launch_scale_dev(n, h->w, dsc + Dsc::HN, 1, h->V + (int64_t)(j + 1) * ld, s);
         }
         if (broke) {
             status = MGR_E_BREAKDOWN;
             break;
         }
         launch_trisolve(k, m, dsc, s);
-        launch_zaxpy(n, k, h->Z, dsc + Dsc::y(0, m), x, s);
+        launch_zaxpy(n, ld, k, h->Z, dsc + Dsc::y(0, m), x, s);
     }
     sync(h);
     if (st) {
@@ -778,7 +790,6 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
             HIPCHK(hipMemcpyAsync(A.v, Ain->values, nnz * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
         }
         h->A0 = opts->transpose ? transpose(h, A, true) : A;
-        h->A0.lanes = choose_lanes(h->A0);
         build_csell(h);
         if (opts->global_relax && h->L > 0) {
             h->binv = dalloc<double>(h, h->ncell * bs * bs);
@@ -808,27 +819,16 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
             Acur = An;
         }
         build_amg(h, h->cg, Acur, opts->amg_pre, opts->amg_post);
-        auto pick = [](DCsr &M) { M.lanes = choose_lanes(M); };
-        auto amg_lanes = [&](AmgHier &H) {
-            for (auto &lv : H.lev) {
-                pick(lv.A);
-                pick(lv.P);
-                pick(lv.PT);
-            }
-        };
-        for (auto &lv : h->lev) {
-            pick(lv.A);
-            pick(lv.P);
-            pick(lv.R);
-            if (lv.ff) amg_lanes(*lv.ff);
-        }
-        amg_lanes(h->cg);
         if (h->o.precision == 1) to_mixed(h);
         alloc_work(h);
         const int m = h->m;
-        h->V = dalloc<double>(h, (int64_t)(m + 1) * n);
-        h->Z = dalloc<double>(h, (int64_t)m * n);
-        h->w = dalloc<double>(h, n);
+        h->ld = krylov_ld(n);
+        h->V = dalloc<double>(h, (int64_t)(m + 1) * h->ld);
+        h->Z = dalloc<double>(h, (int64_t)m * h->ld);
+        h->w = dalloc<double>(h, h->ld);
+        // the padding of V and w beyond n stays zero (the basis kernels read it)
+        launch_fill_f64(h->V, 0.0, (int64_t)(m + 1) * h->ld, h->stream);
+        launch_fill_f64(h->w, 0.0, h->ld, h->stream);
         h->res = dalloc<double>(h, n);
         h->dsc = dalloc<double>(h, Dsc::size(m));
         launch_fill_f64(h->dsc, 0.0, Dsc::size(m), h->stream);

@@ -20,7 +20,6 @@ struct DCsr {
     int32_t *rp = nullptr, *ci = nullptr;
     double *v = nullptr;
     float *vf = nullptr;
-    int lanes = 1;  // threads per row of the row-list kernels (F-point residual / relaxation)
 };
 
 // Cell-sliced ELL of the level-0 operator: 64 consecutive cells form a slice;
@@ -65,6 +64,7 @@ struct MgrLevel {
     double *dinv = nullptr;
     float *dinvf = nullptr;
     bool aff_diag = false;  // A_FF diagonal: the F-relaxation may update in place
+    int flanes = 1;         // threads per F row in the F-point residual / relaxation kernels
     std::shared_ptr<AmgHier> ff;  // AMG V-cycle on A_FF as the F-relaxation (else Jacobi)
     // V-cycle work vectors
     double *e = nullptr, *t = nullptr, *r = nullptr;
@@ -91,6 +91,7 @@ struct mgr_handle {
 
     // Krylov workspace
     int m = 30;
+    int64_t ld = 0;  // stride of the Krylov vectors in V, Z and w
     double *V = nullptr, *Z = nullptr, *w = nullptr, *res = nullptr;
     double *dsc = nullptr;   // device scalars and Hessenberg storage
     double *part = nullptr;  // per-block partial sums
@@ -162,7 +163,7 @@ void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const i
 // SpGEMM C = A B, canonical ascending-k summation.  pass 0 counts into cnt, pass 1 fills.
 // group = lanes per output row (8, 16, 32, 64); rows of A may hold up to group * 8 entries.
 int spgemm_max_row();
-void launch_row_len_max(int64_t m, const int32_t *rp, int *out, hipStream_t s);
+void launch_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx, hipStream_t s);
 void launch_spgemm(int pass, int group, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av,
                    const int32_t *Brp, const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci,
                    double *Cv, int *err, hipStream_t s);
@@ -199,7 +200,7 @@ template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s);
 // F-row residual t[f] = r[i] - (A e)[i], i = flist[f]
 template <typename T>
-void launch_csr_rows_residual(const DCsr &A, const T *vals, int64_t nrows, const int32_t *rows, const T *e,
+void launch_csr_rows_residual(const DCsr &A, int lanes, const T *vals, int64_t nrows, const int32_t *rows, const T *e,
                               const T *r, T *t, hipStream_t s);
 template <typename T>
 void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, hipStream_t s);
@@ -208,7 +209,7 @@ void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T 
 template <typename T>
 void launch_frelax_scatter(int64_t nF, const int32_t *flist, const T *dinv, const T *t, T *e, hipStream_t s);
 template <typename T>
-void launch_frelax_inplace(const DCsr &A, const T *vals, int64_t nF, const int32_t *flist, const T *dinv,
+void launch_frelax_inplace(const DCsr &A, int lanes, const T *vals, int64_t nF, const int32_t *flist, const T *dinv,
                            const T *r, T *e, hipStream_t s);
 template <typename T>
 void launch_div(int64_t n, const T *r, const T *d, T *x, hipStream_t s);
@@ -221,16 +222,24 @@ template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s);
 
 // ---- Krylov kernels (k_krylov.hip) ----
+// The Arnoldi basis V and w are stored with a stride ld: a multiple of 64 elements
+// with zero padding beyond n, so that every vector starts 512-byte aligned and the
+// basis kernels read two elements per 16-byte load (an odd n reads one padding zero).
 constexpr int kRedBlocks = 1024;
+constexpr int kFusedMaxV = 32;  // widest basis of the fused update-and-dot kernel
+int64_t krylov_ld(int64_t n);
 int red_blocks(int64_t n);  // number of partial sums the reduction kernels write
 // partial sums over blocks of <w, V_i> (i < nv) and <w, w>: part[b*(nv+1) + i]
-void launch_mdot(int64_t n, int nv, const double *V, const double *w, double *part, const int *guard,
-                 hipStream_t s);
-// w -= sum_i h[i] V_i and partial <w,w>: part[b]
-void launch_maxpy_norm(int64_t n, int nv, const double *V, const double *h, double *w, double *part,
+void launch_mdot(int64_t n, int64_t ld, int nv, const double *V, const double *w, double *part, hipStream_t s);
+// w -= sum_i h[i] V_i, then partials of <w, V_i> and <w, w> of the updated w in the
+// layout of launch_mdot
+void launch_maxpy_dot(int64_t n, int64_t ld, int nv, const double *V, const double *h, double *w, double *part,
+                      hipStream_t s);
+// w -= sum_i h[i] V_i and partial <w,w>: part[b]; skipped when guard is set and *guard == 0
+void launch_maxpy_norm(int64_t n, int64_t ld, int nv, const double *V, const double *h, double *w, double *part,
                        const int *guard, hipStream_t s);
 // x += sum_i y[i] Z_i
-void launch_zaxpy(int64_t n, int nv, const double *Z, const double *y, double *x, hipStream_t s);
+void launch_zaxpy(int64_t n, int64_t ld, int nv, const double *Z, const double *y, double *x, hipStream_t s);
 void launch_norm_part(int64_t n, const double *a, double *part, hipStream_t s);
 // y = a * scal[0]  (scal device), or y = a / scal[0] when divide
 void launch_scale_dev(int64_t n, const double *a, const double *scal, int divide, double *y, hipStream_t s);
@@ -250,7 +259,8 @@ struct Dsc {
     __host__ __device__ static int sn(int i, int m) { return 64 + (m + 1) * m + (m + 1) + m + i; }
     __host__ __device__ static int y(int i, int m) { return 64 + (m + 1) * m + (m + 1) + 2 * m + i; }
     __host__ __device__ static int hcur(int i, int m) { return 64 + (m + 1) * m + (m + 1) + 3 * m + i; }
-    __host__ __device__ static int size(int m) { return 64 + (m + 1) * m + (m + 1) + 4 * m + 1 + 8; }
+    __host__ __device__ static int h2(int i, int m) { return 64 + (m + 1) * m + (m + 1) + 4 * m + i; }
+    __host__ __device__ static int size(int m) { return 64 + (m + 1) * m + (m + 1) + 5 * m + 1 + 8; }
     // scalar slots
     enum { BNORM = 0, WN0 = 1, WN = 2, GABS = 3, HN = 4, INVH = 5, BETA = 6, RNORM = 7 };
 };
