@@ -312,7 +312,7 @@ void launch_maxpy_dot(int64_t n, int64_t ld, int nv, const double *V, const doub
     else if (nv <= 16) k_maxpy_dot<16><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
     else if (nv <= kFusedMaxV) k_maxpy_dot<kFusedMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
     else {
-        // too wide to hold the basis chunk in registers: update, then dot
+        // too wide to hold the basis values in registers: update, then dot
         k_maxpy_norm<kMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part, nullptr);
         k_mdot<kMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, w, part);
     }

@@ -267,6 +267,10 @@ __global__ void k_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, 
     int64_t f = gtid();
     if (f >= nF) return;
     int64_t i = flist[f];
+    if (!fmap) {
+        cnt[f] = rp[i + 1] - rp[i];
+        return;
+    }
     int c = 0;
     for (int p = rp[i]; p < rp[i + 1]; ++p) c += fmap[ci[p]] >= 0;
     cnt[f] = c;
@@ -279,7 +283,7 @@ __global__ void k_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, c
     int64_t i = flist[f];
     int q = Frp[f];
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int j = fmap[ci[p]];
+        const int j = fmap ? fmap[ci[p]] : ci[p];
         if (j < 0) continue;
         Fci[q] = j;
         Fv[q] = v[p];
@@ -381,23 +385,38 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
     if (!FILL && glane == 0) cnt_or_Crp[row] = count;
 }
 
-// sum and maximum of the lengths of rows list[0..m) (or rows 0..m when list is null);
-// reduced per wavefront first, one integer atomic per wavefront
-__global__ void k_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx) {
-    const int64_t q = gtid();
-    int len = 0;
-    if (q < m) {
+// sum and maximum of the lengths of rows list[0..m) (or rows 0..m when list is null):
+// a fixed grid strides over the rows, reduces per workgroup, and issues one
+// integer atomic per workgroup (so few atomics meet at one address)
+constexpr int kLenStatBlocks = 512;
+constexpr int kLenStatBT = 256;
+__global__ void __launch_bounds__(kLenStatBT) k_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum,
+                                                      int *mx) {
+    __shared__ int ss[kLenStatBT / kWave], sm[kLenStatBT / kWave];
+    int s = 0, x = 0;
+    for (int64_t q = gtid(); q < m; q += (int64_t)gridDim.x * kLenStatBT) {
         const int64_t i = list ? list[q] : q;
-        len = rp[i + 1] - rp[i];
+        const int len = rp[i + 1] - rp[i];
+        s += len;
+        x = len > x ? len : x;
     }
-    int s = len, x = len;
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
         s += __shfl_xor(s, o);
         const int y = __shfl_xor(x, o);
         x = y > x ? y : x;
     }
+    const int wv = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
+        ss[wv] = s;
+        sm[wv] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kLenStatBT / kWave; ++k) {
+            s += ss[k];
+            x = sm[k] > x ? sm[k] : x;
+        }
         if (sum) atomicAdd(sum, s);
         atomicMax(mx, x);
     }
@@ -804,7 +823,10 @@ void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const i
 }
 int spgemm_max_row() { return kWave * kSpgChunks; }
 void launch_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx, hipStream_t s) {
-    if (m > 0) k_row_len_stats<<<nblocks(m, BT), BT, 0, s>>>(m, list, rp, sum, mx);
+    if (m <= 0) return;
+    const unsigned g0 = nblocks(m, kLenStatBT);
+    const unsigned g = g0 < (unsigned)kLenStatBlocks ? g0 : (unsigned)kLenStatBlocks;
+    k_row_len_stats<<<g, kLenStatBT, 0, s>>>(m, list, rp, sum, mx);
 }
 template <bool FILL, int G>
 static void spgemm_g(int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,

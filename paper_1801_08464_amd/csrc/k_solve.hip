@@ -64,24 +64,32 @@ __global__ void __launch_bounds__(256) k_csell(int64_t ncell, int64_t nslice, co
 }
 
 // CSR "stream" SpMV: a workgroup owns ROWS consecutive rows.  Their nonzeros are
-// read as one contiguous, coalesced stream in passes of LDSN entries; within a
-// pass each thread issues the column and value loads of 8 entries before their
-// dependent gathers of x, and stages the products v*x in LDS.  Then thread t sums
-// row rb+t sequentially in ascending column order (a row's entries may span
+// read as one contiguous, coalesced stream in passes of kStreamLds entries; in a
+// pass each thread issues the column and value loads of all its entries before
+// their dependent gathers of x, and stages the products v*x in LDS.  Then thread t
+// sums row rb+t sequentially in ascending column order (a row's entries may span
 // several passes, which run in ascending order).  No padding, any row-length mix,
 // and the same summation order per row as a sequential CSR loop.  The matrix is
 // streamed with non-temporal loads so that it does not evict x from the caches.
-template <int ROWS>
-struct StreamCfg {
-    static constexpr int lds = ROWS >= 256 ? 4096 : 32 * ROWS;
-};
+// Modes: 0 y = Ax; 1 y = r - Ax; 2 y += Ax; 3 y = x + (r - Ax)/d (Jacobi sweep).
+constexpr int kStreamLds = 4096;
+
+template <typename T, int MODE>
+__device__ inline void row_store(int64_t row, T acc, const T *__restrict__ x, const T *__restrict__ r,
+                                 const T *__restrict__ d, T *__restrict__ y) {
+    if (MODE == 0) y[row] = acc;
+    else if (MODE == 1) y[row] = r[row] - acc;
+    else if (MODE == 2) y[row] = y[row] + acc;
+    else y[row] = x[row] + (r[row] - acc) / d[row];
+}
 
 template <typename T, int MODE, int ROWS>
 __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci, const T *__restrict__ v,
                                                      const T *__restrict__ x, const T *__restrict__ r,
                                                      const T *__restrict__ d, T *__restrict__ y) {
-    constexpr int LDSN = StreamCfg<ROWS>::lds;
+    constexpr int LDSN = kStreamLds;
+    constexpr int B = LDSN / ROWS;  // entries per thread per pass
     __shared__ T sh[LDSN];
     const int tid = threadIdx.x;
     const int64_t rb = (int64_t)blockIdx.x * ROWS;
@@ -96,37 +104,33 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
     T acc = 0;
     for (int base = p0; base < p1; base += LDSN) {
         const int lim = base + LDSN < p1 ? base + LDSN : p1;
-        for (int c0 = base; c0 < lim; c0 += 8 * ROWS) {
-            int j[8];
-            T a8[8], x8[8];
+        int j[B];
+        T av[B], xv[B];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int p = c0 + u * ROWS + tid;
-                j[u] = p < lim ? __builtin_nontemporal_load(ci + p) : -1;
-                a8[u] = p < lim ? __builtin_nontemporal_load(v + p) : (T)0;
-            }
+        for (int u = 0; u < B; ++u) {
+            const int p = base + u * ROWS + tid;
+            j[u] = p < lim ? __builtin_nontemporal_load(ci + p) : -1;
+            av[u] = p < lim ? __builtin_nontemporal_load(v + p) : (T)0;
+        }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) x8[u] = j[u] >= 0 ? x[j[u]] : (T)0;
+        for (int u = 0; u < B; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int p = c0 + u * ROWS + tid;
-                if (p < lim) sh[p - base] = a8[u] * x8[u];
-            }
+        for (int u = 0; u < B; ++u) {
+            const int p = base + u * ROWS + tid;
+            if (p < lim) sh[p - base] = av[u] * xv[u];
         }
         __syncthreads();
         const int lo = a > base ? a : base, hi = b < lim ? b : lim;
         for (int p = lo; p < hi; ++p) acc = acc + sh[p - base];
         __syncthreads();
     }
-    if (row < re) {
-        if (MODE == 0) y[row] = acc;
-        else if (MODE == 1) y[row] = r[row] - acc;
-        else if (MODE == 2) y[row] = y[row] + acc;
-        else y[row] = x[row] + (r[row] - acc) / d[row];
-    }
+    if (row < re) row_store<T, MODE>(row, acc, x, r, d, y);
 }
 
-// t[f] = r[i] - (A e)[i] for the listed rows i = rows[f]
+// Row-list kernels on the compact copy of a level's F rows (row f of AF is row
+// rows[f] of the level matrix, all its columns): LANES threads per row, each
+// summing a strided share, then a fixed xor-tree across the lanes.
+// t[f] = r[i] - (A e)[i], i = rows[f]
 template <typename T, int LANES>
 __global__ void __launch_bounds__(256) k_csr_rows_res(int64_t nr, const int32_t *__restrict__ rows,
                                                       const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
@@ -136,17 +140,16 @@ __global__ void __launch_bounds__(256) k_csr_rows_res(int64_t nr, const int32_t 
     const int64_t f = gid / LANES;
     const int sub = (int)(gid % LANES);
     T s = 0;
-    int64_t i = 0;
-    if (f < nr) {
-        i = rows[f];
-        for (int p = rp[i] + sub; p < rp[i + 1]; p += LANES) s = s + v[p] * e[ci[p]];
-    }
+    if (f < nr)
+        for (int p = rp[f] + sub; p < rp[f + 1]; p += LANES) s = s + v[p] * e[ci[p]];
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
-    if (f < nr && sub == 0) t[f] = r[i] - s;
+    if (f < nr && sub == 0) t[f] = r[rows[f]] - s;
 }
 
-// F-relaxation in place when A_FF is diagonal (no F row reads another F point)
+// F-relaxation in place, e[i] += dinv[f] (r[i] - (A e)[i]) for i = flist[f]; valid
+// when A_FF is diagonal (no F row reads another F point, so the update of e[i]
+// races with no other row's reads).  e is read and written: no restrict.
 template <typename T, int LANES>
 __global__ void __launch_bounds__(256) k_frelax_inplace(int64_t nF, const int32_t *__restrict__ flist,
                                                         const int32_t *__restrict__ rp,
@@ -157,14 +160,34 @@ __global__ void __launch_bounds__(256) k_frelax_inplace(int64_t nF, const int32_
     const int64_t f = gid / LANES;
     const int sub = (int)(gid % LANES);
     T s = 0;
-    int64_t i = 0;
-    if (f < nF) {
-        i = flist[f];
-        for (int p = rp[i] + sub; p < rp[i + 1]; p += LANES) s = s + v[p] * e[ci[p]];
-    }
+    if (f < nF)
+        for (int p = rp[f] + sub; p < rp[f + 1]; p += LANES) s = s + v[p] * e[ci[p]];
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
-    if (f < nF && sub == 0) e[i] = e[i] + dinv[f] * (r[i] - s);
+    if (f < nF && sub == 0) {
+        const int64_t i = flist[f];
+        e[i] = e[i] + dinv[f] * (r[i] - s);
+    }
+}
+
+// CSR SpMV for the small levels, where 256-row workgroups would leave most CUs
+// idle: LANES threads per row with strided shares and a fixed xor-tree, so the
+// loads of a row are issued at once and the latency chain is short.  Modes as
+// the stream kernel.
+template <typename T, int MODE, int LANES>
+__global__ void __launch_bounds__(256) k_csr_lanes(int64_t nrows, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const T *__restrict__ v,
+                                                   const T *__restrict__ x, const T *__restrict__ r,
+                                                   const T *__restrict__ d, T *__restrict__ y) {
+    const int64_t gid = gtid();
+    const int64_t row = gid / LANES;
+    const int sub = (int)(gid % LANES);
+    T s = 0;
+    if (row < nrows)
+        for (int p = rp[row] + sub; p < rp[row + 1]; p += LANES) s = s + v[p] * x[ci[p]];
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
+    if (row < nrows && sub == 0) row_store<T, MODE>(row, s, x, r, d, y);
 }
 
 template <typename T>
@@ -245,6 +268,30 @@ __global__ void __launch_bounds__(256) k_lu_solve(int64_t n, const double *__res
     for (int64_t i = tid; i < n; i += blockDim.x) x[i] = (T)y[i];
 }
 
+// the same substitutions for n <= 64 in one wavefront: the factors are copied to
+// LDS first, lane i holds y[i] and y[k] is broadcast by a shuffle, so there are
+// no workgroup barriers (same operations in the same order as the workgroup kernel)
+template <typename T>
+__global__ void __launch_bounds__(kWave) k_lu_solve_wave(int n, const double *__restrict__ lu,
+                                                         const int32_t *__restrict__ perm, const T *__restrict__ b,
+                                                         T *__restrict__ x) {
+    __shared__ double L[kWave * kWave];
+    const int l = threadIdx.x;
+    for (int q = l; q < n * n; q += kWave) L[q] = lu[q];
+    double y = l < n ? (double)b[perm[l]] : 0.0;
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double yk = __shfl(y, k);
+        if (l > k && l < n) y = y - L[l * n + k] * yk;
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        if (l == k) y = y / L[k * n + k];
+        const double yk = __shfl(y, k);
+        if (l < k) y = y - L[l * n + k] * yk;
+    }
+    if (l < n) x[l] = (T)y;
+}
+
 }  // namespace
 
 constexpr int BT = 256;
@@ -277,13 +324,41 @@ static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T
     }
 }
 
-// 256-row workgroups when they fill the chip several times over, else one
-// wavefront per workgroup so that small coarse levels still spread over the CUs
+template <typename T, int MODE>
+static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const T *r, const T *d, T *y,
+                      hipStream_t s) {
+    const unsigned g = nblocks(A.nrows * lanes, BT);
+    switch (lanes) {
+    case 2: k_csr_lanes<T, MODE, 2><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 4: k_csr_lanes<T, MODE, 4><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 8: k_csr_lanes<T, MODE, 8><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 16: k_csr_lanes<T, MODE, 16><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    default: k_csr_lanes<T, MODE, 32><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    }
+}
+
+// below this many rows the lanes-per-row kernel is faster (measured on the 128^3
+// hierarchy: stream everywhere costs 40 % more solve time, lanes on levels of up
+// to 600k rows about 1 % more)
+constexpr int64_t kCsrStreamMinRows = 131072;
+
+// Large levels: 256-row stream workgroups (sequential row sums).  Small levels,
+// where those would leave most CUs idle: several lanes per row.
 template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
     if (A.nrows <= 0) return;
-    if (A.nrows >= (int64_t)256 * 2048) csr_rows<T, 256>(mode, A, vals, x, r, d, y, s);
-    else csr_rows<T, 64>(mode, A, vals, x, r, d, y, s);
+    if (A.nrows >= kCsrStreamMinRows) {
+        csr_rows<T, 256>(mode, A, vals, x, r, d, y, s);
+        return;
+    }
+    const double avg = (double)A.nnz / (double)A.nrows;
+    const int lanes = avg < 3 ? 2 : avg < 6 ? 4 : avg < 12 ? 8 : avg < 24 ? 16 : 32;
+    switch (mode) {
+    case 0: csr_lanes<T, 0>(A, lanes, vals, x, r, d, y, s); break;
+    case 1: csr_lanes<T, 1>(A, lanes, vals, x, r, d, y, s); break;
+    case 2: csr_lanes<T, 2>(A, lanes, vals, x, r, d, y, s); break;
+    default: csr_lanes<T, 3>(A, lanes, vals, x, r, d, y, s); break;
+    }
 }
 
 template <typename T>
@@ -352,7 +427,9 @@ void launch_scatter_add(int64_t n, const int32_t *idx, const T *d, T *e, hipStre
 
 template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s) {
-    if (n > 0) k_lu_solve<T><<<1, BT, (size_t)n * sizeof(double), s>>>(n, lu, perm, b, x);
+    if (n <= 0) return;
+    if (n <= kWave) k_lu_solve_wave<T><<<1, kWave, 0, s>>>((int)n, lu, perm, b, x);
+    else k_lu_solve<T><<<1, BT, (size_t)n * sizeof(double), s>>>(n, lu, perm, b, x);
 }
 
 #define MGR_INSTANTIATE(T)                                                                                      \

@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "mgr_impl.h"
@@ -42,26 +44,32 @@ T *dalloc(mgr_handle *h, int64_t n) {
     return p;
 }
 
-// temporary device buffer released at scope exit
+// temporary device buffer released at scope exit; the release is stream-ordered,
+// so kernels already queued on the stream may still use it
 template <typename T>
 struct Tmp {
     T *p = nullptr;
     hipStream_t s = nullptr;
     Tmp(mgr_handle *h, int64_t n) : s(h->stream) {
-        if (hipMalloc(reinterpret_cast<void **>(&p), (size_t)(n > 0 ? n : 1) * sizeof(T)) != hipSuccess) {
+        if (pool_alloc(h, reinterpret_cast<void **>(&p), (size_t)(n > 0 ? n : 1) * sizeof(T)) != MGR_OK) {
             p = nullptr;
             throw_err(h, MGR_E_OOM, "device allocation failed (temporary)");
         }
     }
     ~Tmp() {
-        if (p) {
-            (void)hipStreamSynchronize(s);  // queued kernels may still read or write it
-            (void)hipFree(p);
-        }
+        if (p) (void)hipFreeAsync(p, s);
     }
     Tmp(const Tmp &) = delete;
     Tmp &operator=(const Tmp &) = delete;
 };
+
+// release a handle-owned buffer before the handle ends (stream-ordered)
+void release(mgr_handle *h, void *p) {
+    if (!p) return;
+    (void)hipFreeAsync(p, h->stream);
+    for (auto &q : h->allocs)
+        if (q == p) q = nullptr;
+}
 
 template <typename T>
 T d2h1(mgr_handle *h, const T *p) {
@@ -196,15 +204,19 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
         throw_err(h, MGR_E_ZERO_FDIAG, msg);
     }
     lv.aff_diag = h->herr[5] == 0;
-    // lanes of the F-row kernels from the mean length of the F rows
-    if (lv.nF > 0) {
-        reset_err(h);
-        launch_row_len_stats(lv.nF, lv.flist, A.rp, h->derr + 1, h->derr + 2, h->stream);
-        read_err(h);
-        DCsr rows;
-        rows.nrows = lv.nF;
-        rows.nnz = h->herr[1];
-        lv.flanes = choose_lanes(rows);
+    // compact copy of the F rows (all columns) for the F-point residual and the
+    // in-place F-relaxation, at the levels whose cycle uses them
+    if (lv.nF > 0 && ((l == 0 && h->o.global_relax) || h->o.f_sweeps > 1)) {
+        Tmp<int32_t> cnt(h, lv.nF);
+        launch_ff_count(lv.nF, lv.flist, A.rp, A.ci, nullptr, cnt.p, h->stream);
+        lv.AF.nrows = lv.nF;
+        lv.AF.ncols = n;
+        lv.AF.rp = dalloc<int32_t>(h, lv.nF + 1);
+        lv.AF.nnz = scan(h, cnt.p, lv.AF.rp, lv.nF);
+        lv.AF.ci = dalloc<int32_t>(h, lv.AF.nnz);
+        lv.AF.v = dalloc<double>(h, lv.AF.nnz);
+        launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
+        lv.flanes = choose_lanes(lv.AF);
     }
     // optional F-relaxation by one AMG V-cycle on A_FF
     if (((h->o.frelax_amg_mask >> l) & 1) && lv.nF > 0) {
@@ -250,13 +262,9 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     {
         DCsr T = spgemm(h, A, lv.P);
         Anext = spgemm(h, lv.R, T);
-        sync(h);
-        (void)hipFree(T.rp);
-        (void)hipFree(T.ci);
-        (void)hipFree(T.v);
-        // T's buffers were registered with the handle; drop them from the list
-        for (auto &p : h->allocs)
-            if (p == T.rp || p == T.ci || p == T.v) p = nullptr;
+        release(h, T.rp);
+        release(h, T.ci);
+        release(h, T.v);
     }
     lab_next = dalloc<int32_t>(h, lv.nC);
     glob_next = dalloc<int32_t>(h, lv.nC);
@@ -302,10 +310,8 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
                 if (h->herr[6] == 0) break;
                 if (h->herr[7] == 0 || round > 100000) throw_err(h, MGR_E_INVALID, "PMIS made no progress");
             }
-            (void)hipFree(ST.rp);
-            (void)hipFree(ST.ci);
-            for (auto &p : h->allocs)
-                if (p == ST.rp || p == ST.ci) p = nullptr;
+            release(h, ST.rp);
+            release(h, ST.ci);
             Tmp<int32_t> isC(h, n), cmap(h, n + 1);
             launch_cf_flags(n, lv.cf, isC.p, h->stream);
             const int64_t nc = scan(h, isC.p, cmap.p, n);
@@ -324,12 +330,9 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
                 lv.PT = transpose(h, lv.P, true);
                 DCsr T = spgemm(h, A, lv.P);
                 DCsr Ac = spgemm(h, lv.PT, T);
-                sync(h);
-                (void)hipFree(T.rp);
-                (void)hipFree(T.ci);
-                (void)hipFree(T.v);
-                for (auto &p : h->allocs)
-                    if (p == T.rp || p == T.ci || p == T.v) p = nullptr;
+                release(h, T.rp);
+                release(h, T.ci);
+                release(h, T.v);
                 lv.l1 = dalloc<double>(h, n);
                 reset_err(h);
                 launch_l1(n, A.rp, A.v, lv.l1, h->derr, h->stream);
@@ -413,6 +416,7 @@ void to_mixed(mgr_handle *h) {
         lv.A.vf = to_f32(h, lv.A.v, lv.A.nnz);
         lv.P.vf = to_f32(h, lv.P.v, lv.P.nnz);
         lv.R.vf = to_f32(h, lv.R.v, lv.R.nnz);
+        if (lv.AF.v) lv.AF.vf = to_f32(h, lv.AF.v, lv.AF.nnz);
         lv.dinvf = to_f32(h, lv.dinv, lv.nF);
         if (lv.ff) amg_to_mixed(h, *lv.ff);
     }
@@ -546,7 +550,7 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
                 P_<T>::fill(e, lv.n, s);
                 have = true;
             } else {
-                launch_csr_rows_residual<T>(lv.A, lv.flanes, Av, lv.nF, lv.flist, e, r, rF, s);
+                launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, rF, s);
             }
             amg_cycle<T>(h, *lv.ff, 0, rF, dF);
             launch_scatter_add<T>(lv.nF, lv.flist, dF, e, s);
@@ -554,9 +558,9 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
             launch_frelax_first<T>(lv.n, lv.fmap, dinv, r, e, s);
             have = true;
         } else if (lv.aff_diag) {
-            launch_frelax_inplace<T>(lv.A, lv.flanes, Av, lv.nF, lv.flist, dinv, r, e, s);
+            launch_frelax_inplace<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, dinv, r, e, s);
         } else {
-            launch_csr_rows_residual<T>(lv.A, lv.flanes, Av, lv.nF, lv.flist, e, r, t, s);
+            launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, t, s);
             launch_frelax_scatter<T>(lv.nF, lv.flist, dinv, t, e, s);
         }
     }
@@ -705,9 +709,9 @@ void fill_stats(mgr_handle *h, mgr_stats *st) {
 
 void destroy_impl(mgr_handle *h) {
     if (!h) return;
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (void *p : h->allocs)
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFreeAsync(p, h->stream);
+    (void)hipStreamSynchronize(h->stream);
     for (auto e : h->ev) (void)hipEventDestroy(e);
     if (h->hsc) (void)hipHostFree(h->hsc);
     if (h->herr) (void)hipHostFree(h->herr);
@@ -850,11 +854,43 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
 }  // namespace
 
 namespace mgr {
-int alloc(mgr_handle *h, void **p, size_t bytes) {
-    if (hipMalloc(p, bytes) != hipSuccess) {
+// Device memory comes from one stream-ordered pool per device, owned by the
+// library: allocations and releases are queued on the handle's stream (no
+// device-wide synchronisation, no driver call once the pool is warm), and memory
+// a handle releases stays in the pool for later handles in the process.
+int pool_alloc(mgr_handle *h, void **p, size_t bytes) {
+    static std::mutex mu;
+    static std::map<int, hipMemPool_t> pools;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MGR_E_HIP;
+    hipMemPool_t pool = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = pools.find(dev);
+        if (it == pools.end()) {
+            hipMemPoolProps props{};
+            props.allocType = hipMemAllocationTypePinned;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = dev;
+            if (hipMemPoolCreate(&pool, &props) != hipSuccess) return MGR_E_HIP;
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            pools[dev] = pool;
+        } else {
+            pool = it->second;
+        }
+    }
+    if (hipMallocFromPoolAsync(p, bytes, pool, h->stream) != hipSuccess) {
         *p = nullptr;
+        (void)hipGetLastError();
         return MGR_E_OOM;
     }
+    return MGR_OK;
+}
+
+int alloc(mgr_handle *h, void **p, size_t bytes) {
+    const int rc = pool_alloc(h, p, bytes);
+    if (rc != MGR_OK) return rc;
     h->allocs.push_back(*p);
     return MGR_OK;
 }

@@ -64,6 +64,7 @@ struct MgrLevel {
     double *dinv = nullptr;
     float *dinvf = nullptr;
     bool aff_diag = false;  // A_FF diagonal: the F-relaxation may update in place
+    DCsr AF;                // compact copy of the F rows (all columns), row f = level row flist[f]
     int flanes = 1;         // threads per F row in the F-point residual / relaxation kernels
     std::shared_ptr<AmgHier> ff;  // AMG V-cycle on A_FF as the F-relaxation (else Jacobi)
     // V-cycle work vectors
@@ -112,6 +113,9 @@ struct mgr_handle {
 namespace mgr {
 
 // ---- helpers (mgr_host.cpp) ----
+// device allocation from the library's stream-ordered pool on h->stream;
+// alloc() also registers the buffer for release when the handle ends
+int pool_alloc(mgr_handle *h, void **p, size_t bytes);
 int alloc(mgr_handle *h, void **p, size_t bytes);
 template <typename T>
 inline int alloc_n(mgr_handle *h, T **p, int64_t n) {
@@ -155,7 +159,8 @@ void launch_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, const in
                    const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Rrp, int32_t *Rci,
                    double *Rv, hipStream_t s);
 void launch_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst, hipStream_t s);
-// A_FF: rows flist, columns with fmap >= 0 renumbered by fmap
+// A_FF: rows flist, columns with fmap >= 0 renumbered by fmap (fmap null: every
+// column kept unrenumbered, the compact copy of the F rows)
 void launch_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
                      int32_t *cnt, hipStream_t s);
 void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
@@ -198,7 +203,8 @@ void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *
 // mode 0: y = A x;  1: y = r - A x;  2: y += A x;  3: y = x + (r - A x) / d (x != y)
 template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s);
-// F-row residual t[f] = r[i] - (A e)[i], i = flist[f]
+// F-row residual t[f] = r[i] - (A e)[i], i = rows[f]; A is the compact F-row copy
+// (its row f is row rows[f] of the level matrix)
 template <typename T>
 void launch_csr_rows_residual(const DCsr &A, int lanes, const T *vals, int64_t nrows, const int32_t *rows, const T *e,
                               const T *r, T *t, hipStream_t s);
@@ -208,6 +214,7 @@ template <typename T>
 void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T *r, T *e, hipStream_t s);
 template <typename T>
 void launch_frelax_scatter(int64_t nF, const int32_t *flist, const T *dinv, const T *t, T *e, hipStream_t s);
+// e[i] += dinv[f] (r[i] - (A e)[i]), i = flist[f], A the compact F-row copy; needs A_FF diagonal
 template <typename T>
 void launch_frelax_inplace(const DCsr &A, int lanes, const T *vals, int64_t nF, const int32_t *flist, const T *dinv,
                            const T *r, T *e, hipStream_t s);
