@@ -87,7 +87,8 @@ def run_form(s, dev, form, steps, warmup, tol, timing=False):
         infos.append(info)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ktime = [k.kernel_time() for k in keep if hasattr(k, "kernel_time")] if timing else []
+    ktime = [k.kernel_time(0) for k in keep if hasattr(k, "kernel_time")] if timing else []
+    vtime = [k.kernel_time(1) for k in keep if hasattr(k, "kernel_time")] if timing else []
     err = None
     if form != "adjoint":
         xt = torch.as_tensor(s.x_true, device=dev)
@@ -113,13 +114,43 @@ def run_form(s, dev, form, steps, warmup, tol, timing=False):
     )
     if err is not None:
         out["rel_error_vs_x_true"] = err
+    def summary(rec):
+        ms = sum(k[0] for k in rec)
+        cnt = sum(k[1] for k in rec)
+        byt = sum(k[2] for k in rec)
+        return dict(total_ms=ms, launches=cnt, avg_us=1e3 * ms / max(cnt, 1), algorithmic_bytes=byt,
+                    bytes_per_launch=byt / max(cnt, 1), achieved_GBs=byt / (ms * 1e-3) / 1e9 if ms > 0 else 0.0)
+
     if ktime:
-        ms = sum(k[0] for k in ktime)
-        cnt = sum(k[1] for k in ktime)
-        byt = sum(k[2] for k in ktime)
-        out["fine_kernel"] = dict(total_ms=ms, launches=cnt, avg_us=1e3 * ms / max(cnt, 1),
-                                  algorithmic_bytes=byt, achieved_GBs=byt / (ms * 1e-3) / 1e9 if ms > 0 else 0)
+        out["fine_kernel"] = summary(ktime)
+    if vtime:
+        v = summary(vtime)
+        v["frac_of_hbm_peak"] = v["achieved_GBs"] / HBM_PEAK_GBS
+        out["vcycle"] = v
     return out
+
+
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_csell_128cube_fp64_hbm_traffic.md")
+FINE_KERNEL_SOURCE = os.path.join(ROOT, "paper_1801_08464_amd", "csrc", "k_fine.hip")
+
+
+def measured_traffic(path, cfg):
+    """HBM bytes per launch of the fine kernel from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE record (calibrated against a plain copy), or None when the record
+    is missing, is for another workload, or the kernel source has changed since."""
+    import hashlib
+    import re
+    path = path or TRAFFIC_RECORD
+    if not os.path.exists(path):
+        return None, "no PMC record"
+    txt = open(path).read()
+    fields = dict(re.findall(r"^- (\w+): (\S+)", txt, re.M))
+    src = hashlib.sha256(open(FINE_KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("source_sha256") != src:
+        return None, "kernel changed since the PMC record"
+    if fields.get("config") != str(cfg):
+        return None, "PMC record is for another workload"
+    return float(fields["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
 
 
 def cpu_baseline(cfg):
@@ -152,7 +183,8 @@ def main():
     ap.add_argument("--forms", default="fp64,mixed,adjoint")
     ap.add_argument("--adjoint-config", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch of the fine kernel")
+    ap.add_argument("--traffic", default=None,
+                    help="rocprofv3 FETCH_SIZE/WRITE_SIZE record of the fine kernel (default: the one under profiles/)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy kernel (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -187,20 +219,18 @@ def main():
                                       "setup on A^T + adjoint solve + pattern scatter"
             del s5
         else:
-            forms[form] = run_form(s, dev, form, args.steps, args.warmup, args.tol, timing=(form == "fp64"))
+            forms[form] = run_form(s, dev, form, args.steps, args.warmup, args.tol, timing=True)
     main_form = forms.get("fp64") or next(iter(forms.values()))
     p = CONFIGS[args.config]
     fk = main_form.get("fine_kernel")
     roof = None
     if fk:
-        traffic = None
-        if args.traffic and os.path.exists(args.traffic):
-            traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+        traffic, traffic_note = measured_traffic(args.traffic, args.config)
         roof = dict(bound="hbm", achieved=fk["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=fk["achieved_GBs"] / HBM_PEAK_GBS, traffic=traffic,
                     kernel="k_csell (level-0 sliced-ELL SpMV / residual, FP64)",
                     avg_us=fk["avg_us"], launches=fk["launches"],
-                    algorithmic_bytes_per_launch=fk["algorithmic_bytes"] / max(fk["launches"], 1))
+                    algorithmic_bytes_per_launch=fk["bytes_per_launch"], traffic_source=traffic_note)
     line = {
         "metric": METRIC,
         "value": main_form["unknowns_per_s"],
@@ -219,6 +249,9 @@ def main():
                                f"{p['region']}; step = mgr_setup + mgr_solve to {args.tol:g}",
                    "restart": 30, "tol": args.tol, "seed": p["seed"]},
         "roofline": roof,
+        "vcycle_hbm": {k: {"achieved_GBs": v["vcycle"]["achieved_GBs"], "frac": v["vcycle"]["frac_of_hbm_peak"],
+                           "avg_us": v["vcycle"]["avg_us"], "bytes_per_apply": v["vcycle"]["bytes_per_launch"]}
+                       for k, v in forms.items() if "vcycle" in v and k != "adjoint"},
         "forms": forms,
     }
     if not args.no_cpu_baseline:

@@ -172,11 +172,16 @@ int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len);
 
 /*
  * Kernel timing: when on, every launch of the level-0 sliced-ELL SpMV /
- * residual kernel is bracketed by HIP events on the handle's stream.
+ * residual kernel, and every whole preconditioner application (the MGR
+ * V-cycle of Section 4, algorithm "MGR preconditioner with presmoothing", inside mgr_solve or
+ * mgr_apply_preconditioner), is bracketed by HIP events on the handle's stream.
  * mgr_kernel_time (synchronises) returns the summed event time, the number of
- * launches and the summed algorithmic bytes of those launches (stored values
- * and column indices of the true nonzeros, row pointers, x, y and r when
- * read), then resets the counters.  kernel: 0 = that kernel (FP64 and FP32).
+ * launches and the summed algorithmic bytes of those launches, then resets the
+ * counters.  kernel: 0 = the level-0 kernel (bytes: stored values and column
+ * indices of the true nonzeros, row pointers, x, y and r when read); 1 = the
+ * V-cycle (bytes: the sum over its launches of every array each reads or
+ * writes, counted once per launch, with gathered vectors at their length).
+ * Returns MGR_E_INVALID for another kernel id.
  */
 int mgr_set_kernel_timing(mgr_handle *h, int on);
 int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launches, double *bytes_total);

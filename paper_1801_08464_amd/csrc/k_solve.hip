@@ -1,67 +1,15 @@
-// Solve-phase kernels: the fine-level SpMV on the cell-sliced ELL, CSR SpMV
-// variants for the coarser MGR levels, R, P and the AMG levels, the relaxations
-// of the MGR V-cycle and the coarsest dense solve.  Templated on the value type
-// (double, or float for the mixed-precision hierarchy).  Every row sum runs in
-// ascending column order per thread; the multi-lane CSR kernels reduce partial
-// sums across lanes, which reorders the additions only.
+// Solve-phase kernels: CSR SpMV variants for the coarser MGR levels, R, P and
+// the AMG levels, the relaxations of the MGR V-cycle and the coarsest dense
+// solve.  Templated on the value type (double, or float for the mixed-precision
+// hierarchy).  The stream kernel sums each row in ascending column order in one
+// thread; the multi-lane kernels reduce strided partial sums across lanes, which
+// reorders the additions only.
 #include "mgr_impl.h"
 
 namespace mgr {
 namespace {
 
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
-
-// Fine-level SpMV on the cell-sliced ELL: one wavefront per 64-cell slice, one
-// thread per cell computing all BS rows of its cell (so each cell's outputs are
-// written together, without partial-line writes).  Each component's slots are
-// read in chunks of 8: every column and value load of a chunk (each a contiguous
-// wavefront segment) is issued before the dependent gathers of x.  Row sums run
-// in ascending column order.
-template <typename T, int MODE, int BS>
-__global__ void __launch_bounds__(256) k_csell(int64_t ncell, int64_t nslice, const int32_t *__restrict__ off,
-                                                    const int32_t *__restrict__ width,
-                                                    const int32_t *__restrict__ col, const T *__restrict__ val,
-                                                    const T *__restrict__ x, const T *__restrict__ r,
-                                                    T *__restrict__ y) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t s = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-    if (s >= nslice) return;
-    const int64_t c = s * kWave + lane;
-    T out[BS];
-#pragma unroll
-    for (int comp = 0; comp < BS; ++comp) {
-        const int64_t g = s * BS + comp;
-        const int64_t o = off[g];
-        const int w = width[g];
-        const int32_t *cp = col + o * kWave + lane;
-        const T *vp = val + o * kWave + lane;
-        T acc = 0;
-        for (int t0 = 0; t0 < w; t0 += 8) {
-            int j[8];
-            T a[8], xv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                j[u] = t0 + u < w ? cp[(int64_t)(t0 + u) * kWave] : -1;
-                a[u] = t0 + u < w ? vp[(int64_t)(t0 + u) * kWave] : (T)0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (j[u] >= 0) acc = acc + a[u] * xv[u];
-        }
-        out[comp] = acc;
-    }
-    if (c < ncell) {
-#pragma unroll
-        for (int comp = 0; comp < BS; ++comp) {
-            const int64_t i = c * BS + comp;
-            if (MODE == 0) y[i] = out[comp];
-            else if (MODE == 1) y[i] = r[i] - out[comp];
-            else y[i] = y[i] + out[comp];
-        }
-    }
-}
 
 // CSR "stream" SpMV: a workgroup owns ROWS consecutive rows.  Their nonzeros are
 // read as one contiguous, coalesced stream in passes of kStreamLds entries; in a
@@ -296,22 +244,6 @@ __global__ void __launch_bounds__(kWave) k_lu_solve_wave(int n, const double *__
 
 constexpr int BT = 256;
 
-template <typename T>
-void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s) {
-    if (A.nslice <= 0) return;
-    const unsigned g = nblocks(A.nslice, BT / kWave);
-#define MGR_CSELL(BS)                                                                                             \
-    do {                                                                                                          \
-        if (mode == 0) k_csell<T, 0, BS><<<g, BT, 0, s>>>(A.ncell, A.nslice, A.off, A.width, A.col, vals, x, r, y); \
-        else if (mode == 1)                                                                                       \
-            k_csell<T, 1, BS><<<g, BT, 0, s>>>(A.ncell, A.nslice, A.off, A.width, A.col, vals, x, r, y);           \
-        else k_csell<T, 2, BS><<<g, BT, 0, s>>>(A.ncell, A.nslice, A.off, A.width, A.col, vals, x, r, y);          \
-    } while (0)
-    if (A.bs == 3) MGR_CSELL(3);
-    else MGR_CSELL(1);
-#undef MGR_CSELL
-}
-
 template <typename T, int ROWS>
 static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y,
                      hipStream_t s) {
@@ -433,7 +365,6 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
 }
 
 #define MGR_INSTANTIATE(T)                                                                                      \
-    template void launch_csell<T>(int, const CSell &, const T *, const T *, const T *, T *, hipStream_t);       \
     template void launch_csr<T>(int, const DCsr &, const T *, const T *, const T *, const T *, T *, hipStream_t); \
     template void launch_csr_rows_residual<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *, \
                                               const T *, T *, hipStream_t);                                     \

@@ -459,31 +459,54 @@ struct P_<float> {
     static void fill(float *p, int64_t n, hipStream_t s) { launch_fill_f32(p, 0.0f, n, s); }
 };
 
+// ---- event timing and algorithmic-byte accounting ----
+// Algorithmic bytes count every array a launch reads or writes once: stored
+// values and column indices, row pointers, the gathered vector at its length,
+// and each dense vector the launch touches.
+hipEvent_t timer_mark(mgr_handle *h, mgr_handle::Timer &t) {
+    if (t.ev.size() <= t.used) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        t.ev.push_back(e);
+    }
+    hipEvent_t e = t.ev[t.used++];
+    HIPCHK(hipEventRecord(e, h->stream));
+    return e;
+}
+
+inline void acct(mgr_handle *h, double bytes) {
+    if (h->timing) h->vc_bytes += bytes;
+}
+
+double csr_bytes(const DCsr &A, int mode, double S) {
+    double b = (double)A.nnz * (S + 4.0) + 4.0 * (double)(A.nrows + 1) + S * (double)A.ncols + S * (double)A.nrows;
+    if (mode == 1 || mode == 2) b += S * (double)A.nrows;
+    if (mode == 3) b += 2.0 * S * (double)A.nrows;
+    return b;
+}
+
 // the fine-level sliced-ELL kernel, optionally bracketed by events for timing
 template <typename T>
 void fine_op(mgr_handle *h, int mode, const T *x, const T *r, T *y) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (h->timing) {
-        while (h->ev.size() < h->ev_used + 2) {
-            hipEvent_t e;
-            HIPCHK(hipEventCreate(&e));
-            h->ev.push_back(e);
-        }
-        e0 = h->ev[h->ev_used];
-        e1 = h->ev[h->ev_used + 1];
-        h->ev_used += 2;
-        HIPCHK(hipEventRecord(e0, h->stream));
-    }
+    if (h->timing) timer_mark(h, h->tm[0]);
     launch_csell<T>(mode, h->A0s, P_<T>::v(h->A0s), x, r, y, h->stream);
     if (h->timing) {
-        HIPCHK(hipEventRecord(e1, h->stream));
-        // algorithmic bytes: values + columns of the true nonzeros, row pointers,
-        // x and y, plus r for the residual form
+        timer_mark(h, h->tm[0]);
+        // values + columns of the true nonzeros, row pointers, x and y, plus r
+        // for the residual form
         const double n = (double)h->n;
-        h->t_bytes += (double)h->A0s.nnz_true * (sizeof(T) + 4.0) + 4.0 * (n + 1) + 2.0 * n * sizeof(T) +
-                      (mode == 1 ? n * sizeof(T) : 0.0);
-        h->t_launches++;
+        const double b = (double)h->A0s.nnz_true * (sizeof(T) + 4.0) + 4.0 * (n + 1) + 2.0 * n * sizeof(T) +
+                         (mode == 1 ? n * sizeof(T) : 0.0);
+        h->tm[0].bytes += b;
+        h->tm[0].launches++;
+        h->vc_bytes += b;
     }
+}
+
+template <typename T>
+void csr(mgr_handle *h, int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y) {
+    launch_csr<T>(mode, A, vals, x, r, d, y, h->stream);
+    acct(h, csr_bytes(A, mode, sizeof(T)));
 }
 
 template <typename T>
@@ -491,8 +514,10 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x) {
     AmgLevel &lv = H.lev[k];
     hipStream_t s = h->stream;
     const int64_t n = lv.n;
+    const double S = sizeof(T);
     if (k == (int)H.lev.size() - 1) {
         launch_lu_solve<T>(n, H.lu, H.perm, r, x, s);
+        acct(h, 8.0 * n * n + 4.0 * n + 2.0 * S * n);
         return;
     }
     const T *Av = P_<T>::v(lv.A);
@@ -505,20 +530,24 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x) {
     for (int it = 0; it < pre; ++it) {
         if (it == 0) {
             launch_div<T>(n, r, l1, cur, s);
+            acct(h, 3.0 * S * n);
         } else {
-            launch_csr<T>(3, lv.A, Av, cur, r, l1, oth, s);
+            csr<T>(h, 3, lv.A, Av, cur, r, l1, oth);
             std::swap(cur, oth);
         }
     }
-    if (pre == 0) P_<T>::fill(cur, n, s);
+    if (pre == 0) {
+        P_<T>::fill(cur, n, s);
+        acct(h, S * n);
+    }
     T *t = P_<T>::t(lv);
-    launch_csr<T>(1, lv.A, Av, cur, r, nullptr, t, s);
+    csr<T>(h, 1, lv.A, Av, cur, r, nullptr, t);
     AmgLevel &nx = H.lev[k + 1];
-    launch_csr<T>(0, lv.PT, P_<T>::v(lv.PT), t, nullptr, nullptr, P_<T>::r(nx), s);
+    csr<T>(h, 0, lv.PT, P_<T>::v(lv.PT), t, nullptr, nullptr, P_<T>::r(nx));
     amg_cycle<T>(h, H, k + 1, P_<T>::r(nx), P_<T>::x(nx));
-    launch_csr<T>(2, lv.P, P_<T>::v(lv.P), P_<T>::x(nx), nullptr, nullptr, cur, s);
+    csr<T>(h, 2, lv.P, P_<T>::v(lv.P), P_<T>::x(nx), nullptr, nullptr, cur);
     for (int it = 0; it < post; ++it) {
-        launch_csr<T>(3, lv.A, Av, cur, r, l1, oth, s);
+        csr<T>(h, 3, lv.A, Av, cur, r, l1, oth);
         std::swap(cur, oth);
     }
 }
@@ -534,10 +563,14 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
     const T *Av = P_<T>::v(lv.A);
     const T *dinv = P_<T>::dinv(lv);
     T *t = P_<T>::t(lv);
+    const double S = sizeof(T), n = (double)lv.n, nF = (double)lv.nF;
+    // bytes of a compact F-row product (values, columns, row pointers, F list, e gathered)
+    const double afb = (double)lv.AF.nnz * (S + 4.0) + 4.0 * (nF + 1.0) + 4.0 * nF + S * n;
     bool have = false;
     // (1) global relaxation with the cell blocks (level 0)
     if (l == 0 && h->o.global_relax) {
         launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), r, e, s);
+        acct(h, (double)h->bs * h->bs * S * h->ncell + 2.0 * S * n);
         have = true;
     }
     // (2) F-relaxation: Jacobi with diag(A_FF), or one AMG V-cycle on A_FF
@@ -548,26 +581,35 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
             if (!have) {
                 launch_gather<T>(lv.nF, lv.flist, r, rF, s);
                 P_<T>::fill(e, lv.n, s);
+                acct(h, 4.0 * nF + 2.0 * S * nF + S * n);
                 have = true;
             } else {
                 launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, rF, s);
+                acct(h, afb + 2.0 * S * nF);
             }
             amg_cycle<T>(h, *lv.ff, 0, rF, dF);
             launch_scatter_add<T>(lv.nF, lv.flist, dF, e, s);
+            acct(h, 4.0 * nF + 3.0 * S * nF);
         } else if (!have) {
             launch_frelax_first<T>(lv.n, lv.fmap, dinv, r, e, s);
+            acct(h, 4.0 * n + S * nF + 2.0 * S * n);
             have = true;
         } else if (lv.aff_diag) {
             launch_frelax_inplace<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, dinv, r, e, s);
+            acct(h, afb + 3.0 * S * nF);
         } else {
             launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, t, s);
             launch_frelax_scatter<T>(lv.nF, lv.flist, dinv, t, e, s);
+            acct(h, afb + 2.0 * S * nF + 4.0 * nF + 4.0 * S * nF);
         }
     }
-    if (!have) P_<T>::fill(e, lv.n, s);
+    if (!have) {
+        P_<T>::fill(e, lv.n, s);
+        acct(h, S * n);
+    }
     // (3) coarse-grid correction e += P M_c^{-1} R (r - A e)
     if (l == 0) fine_op<T>(h, 1, e, r, t);
-    else launch_csr<T>(1, lv.A, Av, e, r, nullptr, t, s);
+    else csr<T>(h, 1, lv.A, Av, e, r, nullptr, t);
     T *rc, *ec;
     if (l + 1 < h->L) {
         rc = P_<T>::r(h->lev[l + 1]);
@@ -576,20 +618,30 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
         rc = P_<T>::r(h->cg.lev[0]);
         ec = P_<T>::x(h->cg.lev[0]);
     }
-    launch_csr<T>(0, lv.R, P_<T>::v(lv.R), t, nullptr, nullptr, rc, s);
+    csr<T>(h, 0, lv.R, P_<T>::v(lv.R), t, nullptr, nullptr, rc);
     mgr_cycle<T>(h, l + 1, rc, ec);
-    launch_csr<T>(2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e, s);
+    csr<T>(h, 2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
 }
 
 void apply_prec(mgr_handle *h, const double *v, double *z) {
+    if (h->timing) {
+        timer_mark(h, h->tm[1]);
+        h->vc_bytes = 0;
+    }
     if (h->o.precision == 1) {
         float *rf = h->L > 0 ? h->lev[0].rf : h->cg.lev[0].rf;
         float *ef = h->L > 0 ? h->lev[0].ef : h->cg.lev[0].xf;
         launch_cast_f64_f32(v, rf, h->n, h->stream);
         mgr_cycle<float>(h, 0, rf, ef);
         launch_cast_f32_f64(ef, z, h->n, h->stream);
+        acct(h, 24.0 * h->n);
     } else {
         mgr_cycle<double>(h, 0, v, z);
+    }
+    if (h->timing) {
+        timer_mark(h, h->tm[1]);
+        h->tm[1].bytes += h->vc_bytes;
+        h->tm[1].launches++;
     }
 }
 
@@ -712,7 +764,8 @@ void destroy_impl(mgr_handle *h) {
     for (void *p : h->allocs)
         if (p) (void)hipFreeAsync(p, h->stream);
     (void)hipStreamSynchronize(h->stream);
-    for (auto e : h->ev) (void)hipEventDestroy(e);
+    for (auto &t : h->tm)
+        for (auto e : t.ev) (void)hipEventDestroy(e);
     if (h->hsc) (void)hipHostFree(h->hsc);
     if (h->herr) (void)hipHostFree(h->herr);
     delete h;
@@ -1104,28 +1157,31 @@ int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len) 
 int mgr_set_kernel_timing(mgr_handle *h, int on) {
     if (!h) return MGR_E_INVALID;
     h->timing = on != 0;
-    h->ev_used = 0;
-    h->t_bytes = 0;
-    h->t_launches = 0;
+    for (auto &t : h->tm) {
+        t.used = 0;
+        t.bytes = 0;
+        t.launches = 0;
+    }
     return MGR_OK;
 }
 
 int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launches, double *bytes_total) {
-    if (!h || kernel != 0) return MGR_E_INVALID;
+    if (!h || kernel < 0 || kernel > 1) return MGR_E_INVALID;
     try {
         sync(h);
+        mgr_handle::Timer &t = h->tm[kernel];
         double tot = 0.0;
-        for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+        for (size_t i = 0; i + 1 < t.used; i += 2) {
             float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
+            HIPCHK(hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
             tot += ms;
         }
         if (total_ms) *total_ms = tot;
-        if (launches) *launches = h->t_launches;
-        if (bytes_total) *bytes_total = h->t_bytes;
-        h->ev_used = 0;
-        h->t_bytes = 0;
-        h->t_launches = 0;
+        if (launches) *launches = t.launches;
+        if (bytes_total) *bytes_total = t.bytes;
+        t.used = 0;
+        t.bytes = 0;
+        t.launches = 0;
         return MGR_OK;
     } catch (const Fail &f) {
         return f.code;

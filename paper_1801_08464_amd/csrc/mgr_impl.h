@@ -101,12 +101,17 @@ struct mgr_handle {
     int *derr = nullptr;     // device error words
     int *herr = nullptr;     // pinned host copy
 
-    // timing of the fine-level kernel
+    // event timing (mgr_set_kernel_timing): tm[0] the level-0 sliced-ELL kernel,
+    // tm[1] whole preconditioner applications (the V-cycle)
+    struct Timer {
+        std::vector<hipEvent_t> ev;
+        size_t used = 0;
+        double bytes = 0;
+        int64_t launches = 0;
+    };
     bool timing = false;
-    std::vector<hipEvent_t> ev;
-    size_t ev_used = 0;
-    double t_bytes = 0;
-    int64_t t_launches = 0;
+    Timer tm[2];
+    double vc_bytes = 0;  // algorithmic bytes of the V-cycle being recorded
     double setup_ms = 0;
 };
 

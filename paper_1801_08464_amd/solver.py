@@ -172,9 +172,11 @@ class MGRSolver:
     def set_kernel_timing(self, on=True):
         self._check(self.lib.mgr_set_kernel_timing(self.h, int(on)))
 
-    def kernel_time(self):
+    def kernel_time(self, kernel=0):
+        """(total ms, launches, algorithmic bytes) since timing was switched on or
+        last read; kernel 0 = level-0 sliced-ELL kernel, 1 = whole V-cycles."""
         ms, cnt, byt = C.c_double(), C.c_int64(), C.c_double()
-        self._check(self.lib.mgr_kernel_time(self.h, 0, C.byref(ms), C.byref(cnt), C.byref(byt)))
+        self._check(self.lib.mgr_kernel_time(self.h, int(kernel), C.byref(ms), C.byref(cnt), C.byref(byt)))
         return ms.value, cnt.value, byt.value
 
 
