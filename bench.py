@@ -173,6 +173,51 @@ def cpu_baseline(cfg):
                 cpu=platform.processor() or platform.machine())
 
 
+# R/P and cycle variants of the MGR preconditioner (Section 4): each changes one
+# choice of the default above
+VARIANTS = {
+    "default": {},
+    "injective": dict(rp_type=1),                  # W_r = 0 (eq. injective_rp)
+    "block_factorization": dict(rp_type=2),        # W_p = 0 (Section 4, last paragraph)
+    "post_smoothing": dict(cycle_post=1),          # eq. MGR-post
+    "f_sweeps_2": dict(f_sweeps=2),                # two F-relaxation sweeps per level
+    "jacobi_frelax": dict(frelax_amg_mask=0),      # Jacobi F-relaxation at every level
+}
+
+
+def run_variants(dev, configs, tol, warmup):
+    import torch
+
+    from paper_1801_08464_amd.solver import MGRSolver
+    from synth import make_config
+    rows = []
+    for cfg in configs:
+        s = make_config(cfg)
+        rp, ci = torch.as_tensor(s.indptr, device=dev), torch.as_tensor(s.indices, device=dev)
+        vals, lab = torch.as_tensor(s.data, device=dev), torch.as_tensor(s.labels, device=dev)
+        b = torch.as_tensor(s.b, device=dev)
+        for name, var in VARIANTS.items():
+            for prec in ("fp64", "mixed"):
+                opts = dict(SOLVER_OPTS) | var
+                for w in range(warmup + 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    g = MGRSolver(rp, ci, vals, lab, precision=prec, **opts)
+                    x, info = g.solve(b, tol)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    g.close()
+                rows.append(dict(config=cfg, variant=name, precision=prec, options=var, status=info.status,
+                                 iterations=info.iterations, rel_residual=info.rel_residual,
+                                 setup_ms=info.setup_ms, solve_ms=info.solve_ms, step_ms=1e3 * dt,
+                                 unknowns_per_s=s.n / dt))
+                log(f"variant cfg {cfg} {name:20s} {prec:5s} status {info.status} its {info.iterations:4d} "
+                    f"setup {info.setup_ms:7.1f} ms solve {info.solve_ms:8.1f} ms")
+        del s, rp, ci, vals, lab, b
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +230,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=None,
                     help="rocprofv3 FETCH_SIZE/WRITE_SIZE record of the fine kernel (default: the one under profiles/)")
+    ap.add_argument("--variants", default=None,
+                    help="comma-separated configs: time the R/P and cycle variants of the preconditioner "
+                         "against the default on them (prints one JSON line with the table)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy kernel (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -199,6 +247,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.variants:
+        cfgs = [int(c) for c in args.variants.split(",")]
+        rows = run_variants(dev, cfgs, args.tol, args.warmup)
+        print(json.dumps({"variants": rows, "tol": args.tol, "base_options": SOLVER_OPTS}))
+        return
     if args.copy_calibration:
         src = torch.ones(64 << 20, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

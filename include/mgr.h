@@ -81,6 +81,10 @@ typedef struct {
                                  (the paper's F-relaxation of its phase-transition runs, Section 6.2)
                                  instead of Jacobi; default 0 */
     int frelax_amg_pre, frelax_amg_post;  /* smoothing sweeps of that V-cycle, default 1, 1 */
+    int cycle_post;           /* 0: pre-smoothing form eq. MGR-pre (Section 4 algorithm "MGR preconditioner
+                                 with presmoothing", default); 1: post-smoothing form eq. MGR-post: the
+                                 coarse-grid correction from e = 0 first, then F-relaxation, then (level 0)
+                                 the global relaxation */
 } mgr_options;
 
 typedef struct {

@@ -80,6 +80,7 @@ void orc_default_opts(orc_opts *o) {
     o->frelax_amg_mask = 0;
     o->frelax_amg_pre = 1;
     o->frelax_amg_post = 1;
+    o->cycle_post = 0;
 }
 
 static double now_ms(void) {

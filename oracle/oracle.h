@@ -48,6 +48,7 @@ typedef struct {
     int use_x0;
     int frelax_amg_mask;  /* bit l set: F-relaxation of MGR level l by one AMG V-cycle on A_FF */
     int frelax_amg_pre, frelax_amg_post;
+    int cycle_post;       /* 1: post-smoothing form eq. MGR-post (coarse correction, then smoothing) */
 } orc_opts;
 
 typedef struct {

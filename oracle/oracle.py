@@ -32,7 +32,8 @@ class _Opts(C.Structure):
                 ("f_sweeps", C.c_int), ("amg_theta", C.c_double), ("amg_pre", C.c_int), ("amg_post", C.c_int),
                 ("amg_max_levels", C.c_int), ("amg_coarse_max", C.c_int), ("dense_max", C.c_int),
                 ("pmis_seed", C.c_uint64), ("precision", C.c_int), ("use_x0", C.c_int),
-                ("frelax_amg_mask", C.c_int), ("frelax_amg_pre", C.c_int), ("frelax_amg_post", C.c_int)]
+                ("frelax_amg_mask", C.c_int), ("frelax_amg_pre", C.c_int), ("frelax_amg_post", C.c_int),
+                ("cycle_post", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -223,7 +224,7 @@ def pattern_outer(A: CSR, lam, x):
 
 DEFAULTS = dict(restart=30, max_iter=400, rp_type=0, global_relax=1, f_sweeps=1, amg_theta=0.25, amg_pre=2,
                 amg_post=2, amg_max_levels=25, amg_coarse_max=64, dense_max=4096, pmis_seed=0, precision=0,
-                use_x0=0, frelax_amg_mask=0, frelax_amg_pre=1, frelax_amg_post=1)
+                use_x0=0, frelax_amg_mask=0, frelax_amg_pre=1, frelax_amg_post=1, cycle_post=0)
 
 
 class OracleError(RuntimeError):

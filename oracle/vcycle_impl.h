@@ -81,6 +81,42 @@ static void FN(amg_cycle)(const amg_hier *H, int k, const REAL *r, REAL *x) {
     free(ec);
 }
 
+/* e += blockdiag(A_0)^{-1} v with the cell blocks (global relaxation) */
+static void FN(block_apply_add)(orc_handle *h, const REAL *v, REAL *e) {
+    const REAL *bi = VALS2(h->binv, h->binvf);
+    if (h->bs == 3) {
+        for (int64_t c = 0; c < h->ncell; ++c) {
+            const REAL *B = bi + 9 * c;
+            const REAL *vv = v + 3 * c;
+            for (int q = 0; q < 3; ++q)
+                e[3 * c + q] = e[3 * c + q] + (B[3 * q] * vv[0] + B[3 * q + 1] * vv[1] + B[3 * q + 2] * vv[2]);
+        }
+    } else {
+        for (int64_t c = 0; c < h->ncell; ++c) e[c] = e[c] + bi[c] * v[c];
+    }
+}
+
+/* F-relaxation sweeps: e_F += M_FF^{-1} (r - A e)_F with M_FF = diag(A_FF)
+ * (Jacobi) or one AMG V-cycle on A_FF */
+static void FN(frelax)(orc_handle *h, mgr_lev *lv, const REAL *Av, const REAL *dinv, const REAL *r, REAL *e,
+                       REAL *tf, REAL *df) {
+    const int64_t nF = lv->nF;
+    for (int s = 0; s < h->o.f_sweeps; ++s) {
+        for (int64_t f = 0; f < nF; ++f) {
+            int64_t i = lv->flist[f];
+            REAL acc = 0;
+            for (int64_t p = lv->A.rp[i]; p < lv->A.rp[i + 1]; ++p) acc += Av[p] * e[lv->A.ci[p]];
+            tf[f] = r[i] - acc;
+        }
+        if (lv->ff) {
+            FN(amg_cycle)(lv->ff, 0, tf, df);
+            for (int64_t f = 0; f < nF; ++f) e[lv->flist[f]] = e[lv->flist[f]] + df[f];
+        } else {
+            for (int64_t f = 0; f < nF; ++f) e[lv->flist[f]] = e[lv->flist[f]] + dinv[f] * tf[f];
+        }
+    }
+}
+
 static void FN(mgr_cycle)(orc_handle *h, int l, const REAL *r, REAL *e) {
     if (l == h->L) {
         FN(amg_cycle)(&h->cg, 0, r, e);
@@ -96,40 +132,29 @@ static void FN(mgr_cycle)(orc_handle *h, int l, const REAL *r, REAL *e) {
     REAL *tf = (REAL *)malloc((size_t)(nF > 0 ? nF : 1) * sizeof(REAL));
     REAL *df = (REAL *)malloc((size_t)(nF > 0 ? nF : 1) * sizeof(REAL));
     for (int64_t i = 0; i < nU; ++i) e[i] = 0;
-    /* (1) global relaxation e = blockdiag(A)^{-1} r (level 0 only) */
-    if (l == 0 && h->o.global_relax) {
-        const REAL *bi = VALS2(h->binv, h->binvf);
-        if (h->bs == 3) {
-            for (int64_t c = 0; c < h->ncell; ++c) {
-                const REAL *B = bi + 9 * c;
-                const REAL *rr = r + 3 * c;
-                for (int q = 0; q < 3; ++q) e[3 * c + q] = B[3 * q] * rr[0] + B[3 * q + 1] * rr[1] + B[3 * q + 2] * rr[2];
-            }
-        } else {
-            for (int64_t c = 0; c < h->ncell; ++c) e[c] = bi[c] * r[c];
+    if (h->o.cycle_post) {
+        /* post-smoothing form, eq. MGR-post: the coarse-grid correction from e = 0
+         * first, then the smoother, whose two steps run in the reverse order of the
+         * pre-smoothing algorithm (F-relaxation, then the level-0 global relaxation) */
+        FN(spmv)(&lv->R, VALS(lv->R, lv->Rf), r, rc);
+        FN(mgr_cycle)(h, l + 1, rc, ec);
+        FN(spmv_add)(&lv->P, VALS(lv->P, lv->Pf), ec, e);
+        FN(frelax)(h, lv, Av, dinv, r, e, tf, df);
+        if (l == 0 && h->o.global_relax) {
+            FN(residual)(&lv->A, Av, r, e, rho);
+            FN(block_apply_add)(h, rho, e);
         }
+    } else {
+        /* (1) global relaxation e = blockdiag(A)^{-1} r (level 0 only) */
+        if (l == 0 && h->o.global_relax) FN(block_apply_add)(h, r, e);
+        /* (2) F-relaxation */
+        FN(frelax)(h, lv, Av, dinv, r, e, tf, df);
+        /* (3) coarse-grid correction e += P M_c^{-1} R (r - A e) */
+        FN(residual)(&lv->A, Av, r, e, rho);
+        FN(spmv)(&lv->R, VALS(lv->R, lv->Rf), rho, rc);
+        FN(mgr_cycle)(h, l + 1, rc, ec);
+        FN(spmv_add)(&lv->P, VALS(lv->P, lv->Pf), ec, e);
     }
-    /* (2) F-relaxation: e_F += M_FF^{-1} (r - A e)_F with M_FF = diag(A_FF)
-     *     (Jacobi) or one AMG V-cycle on A_FF */
-    for (int s = 0; s < h->o.f_sweeps; ++s) {
-        for (int64_t f = 0; f < nF; ++f) {
-            int64_t i = lv->flist[f];
-            REAL acc = 0;
-            for (int64_t p = lv->A.rp[i]; p < lv->A.rp[i + 1]; ++p) acc += Av[p] * e[lv->A.ci[p]];
-            tf[f] = r[i] - acc;
-        }
-        if (lv->ff) {
-            FN(amg_cycle)(lv->ff, 0, tf, df);
-            for (int64_t f = 0; f < nF; ++f) e[lv->flist[f]] = e[lv->flist[f]] + df[f];
-        } else {
-            for (int64_t f = 0; f < nF; ++f) e[lv->flist[f]] = e[lv->flist[f]] + dinv[f] * tf[f];
-        }
-    }
-    /* (3) coarse-grid correction e += P M_c^{-1} R (r - A e) */
-    FN(residual)(&lv->A, Av, r, e, rho);
-    FN(spmv)(&lv->R, VALS(lv->R, lv->Rf), rho, rc);
-    FN(mgr_cycle)(h, l + 1, rc, ec);
-    FN(spmv_add)(&lv->P, VALS(lv->P, lv->Pf), ec, e);
     free(rho);
     free(rc);
     free(ec);

@@ -138,20 +138,23 @@ __global__ void __launch_bounds__(256) k_csr_lanes(int64_t nrows, const int32_t 
     if (row < nrows && sub == 0) row_store<T, MODE>(row, s, x, r, d, y);
 }
 
-template <typename T>
+// e = B^{-1} r per cell (ADD: e += B^{-1} r)
+template <typename T, bool ADD>
 __global__ void k_block_apply3(int64_t ncell, const T *__restrict__ B, const T *__restrict__ r, T *__restrict__ e) {
     const int64_t c = gtid();
     if (c >= ncell) return;
     const T r0 = r[3 * c], r1 = r[3 * c + 1], r2 = r[3 * c + 2];
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-        e[3 * c + q] = B[(3 * q) * ncell + c] * r0 + B[(3 * q + 1) * ncell + c] * r1 + B[(3 * q + 2) * ncell + c] * r2;
+    for (int q = 0; q < 3; ++q) {
+        const T d = B[(3 * q) * ncell + c] * r0 + B[(3 * q + 1) * ncell + c] * r1 + B[(3 * q + 2) * ncell + c] * r2;
+        e[3 * c + q] = ADD ? e[3 * c + q] + d : d;
+    }
 }
 
-template <typename T>
+template <typename T, bool ADD>
 __global__ void k_block_apply1(int64_t ncell, const T *__restrict__ B, const T *__restrict__ r, T *__restrict__ e) {
     const int64_t c = gtid();
-    if (c < ncell) e[c] = B[c] * r[c];
+    if (c < ncell) e[c] = ADD ? e[c] + B[c] * r[c] : B[c] * r[c];
 }
 
 template <typename T>
@@ -326,10 +329,16 @@ void launch_frelax_inplace(const DCsr &A, int lanes, const T *vals, int64_t nF, 
 }
 
 template <typename T>
-void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, hipStream_t s) {
+void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, bool add, hipStream_t s) {
     if (ncell <= 0) return;
-    if (bs == 3) k_block_apply3<T><<<nblocks(ncell, BT), BT, 0, s>>>(ncell, binv, r, e);
-    else k_block_apply1<T><<<nblocks(ncell, BT), BT, 0, s>>>(ncell, binv, r, e);
+    const unsigned g = nblocks(ncell, BT);
+    if (bs == 3) {
+        if (add) k_block_apply3<T, true><<<g, BT, 0, s>>>(ncell, binv, r, e);
+        else k_block_apply3<T, false><<<g, BT, 0, s>>>(ncell, binv, r, e);
+    } else {
+        if (add) k_block_apply1<T, true><<<g, BT, 0, s>>>(ncell, binv, r, e);
+        else k_block_apply1<T, false><<<g, BT, 0, s>>>(ncell, binv, r, e);
+    }
 }
 
 template <typename T>
@@ -370,7 +379,7 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
                                               const T *, T *, hipStream_t);                                     \
     template void launch_frelax_inplace<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *,   \
                                            const T *, T *, hipStream_t);                                        \
-    template void launch_block_apply<T>(int64_t, int, const T *, const T *, T *, hipStream_t);                  \
+    template void launch_block_apply<T>(int64_t, int, const T *, const T *, T *, bool, hipStream_t);            \
     template void launch_frelax_first<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);     \
     template void launch_frelax_scatter<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);   \
     template void launch_div<T>(int64_t, const T *, const T *, T *, hipStream_t);                               \

@@ -206,7 +206,7 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     lv.aff_diag = h->herr[5] == 0;
     // compact copy of the F rows (all columns) for the F-point residual and the
     // in-place F-relaxation, at the levels whose cycle uses them
-    if (lv.nF > 0 && ((l == 0 && h->o.global_relax) || h->o.f_sweeps > 1)) {
+    if (lv.nF > 0 && ((l == 0 && h->o.global_relax) || h->o.f_sweeps > 1 || h->o.cycle_post)) {
         Tmp<int32_t> cnt(h, lv.nF);
         launch_ff_count(lv.nF, lv.flist, A.rp, A.ci, nullptr, cnt.p, h->stream);
         lv.AF.nrows = lv.nF;
@@ -566,50 +566,6 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
     const double S = sizeof(T), n = (double)lv.n, nF = (double)lv.nF;
     // bytes of a compact F-row product (values, columns, row pointers, F list, e gathered)
     const double afb = (double)lv.AF.nnz * (S + 4.0) + 4.0 * (nF + 1.0) + 4.0 * nF + S * n;
-    bool have = false;
-    // (1) global relaxation with the cell blocks (level 0)
-    if (l == 0 && h->o.global_relax) {
-        launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), r, e, s);
-        acct(h, (double)h->bs * h->bs * S * h->ncell + 2.0 * S * n);
-        have = true;
-    }
-    // (2) F-relaxation: Jacobi with diag(A_FF), or one AMG V-cycle on A_FF
-    for (int sw = 0; sw < h->o.f_sweeps; ++sw) {
-        if (lv.ff) {
-            AmgLevel &f0 = lv.ff->lev[0];
-            T *rF = P_<T>::r(f0), *dF = P_<T>::x(f0);
-            if (!have) {
-                launch_gather<T>(lv.nF, lv.flist, r, rF, s);
-                P_<T>::fill(e, lv.n, s);
-                acct(h, 4.0 * nF + 2.0 * S * nF + S * n);
-                have = true;
-            } else {
-                launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, rF, s);
-                acct(h, afb + 2.0 * S * nF);
-            }
-            amg_cycle<T>(h, *lv.ff, 0, rF, dF);
-            launch_scatter_add<T>(lv.nF, lv.flist, dF, e, s);
-            acct(h, 4.0 * nF + 3.0 * S * nF);
-        } else if (!have) {
-            launch_frelax_first<T>(lv.n, lv.fmap, dinv, r, e, s);
-            acct(h, 4.0 * n + S * nF + 2.0 * S * n);
-            have = true;
-        } else if (lv.aff_diag) {
-            launch_frelax_inplace<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, dinv, r, e, s);
-            acct(h, afb + 3.0 * S * nF);
-        } else {
-            launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, t, s);
-            launch_frelax_scatter<T>(lv.nF, lv.flist, dinv, t, e, s);
-            acct(h, afb + 2.0 * S * nF + 4.0 * nF + 4.0 * S * nF);
-        }
-    }
-    if (!have) {
-        P_<T>::fill(e, lv.n, s);
-        acct(h, S * n);
-    }
-    // (3) coarse-grid correction e += P M_c^{-1} R (r - A e)
-    if (l == 0) fine_op<T>(h, 1, e, r, t);
-    else csr<T>(h, 1, lv.A, Av, e, r, nullptr, t);
     T *rc, *ec;
     if (l + 1 < h->L) {
         rc = P_<T>::r(h->lev[l + 1]);
@@ -618,6 +574,72 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
         rc = P_<T>::r(h->cg.lev[0]);
         ec = P_<T>::x(h->cg.lev[0]);
     }
+    // F-relaxation sweeps: Jacobi with diag(A_FF), or one AMG V-cycle on A_FF;
+    // `have` tells whether e already holds a value (else e = 0 is implied)
+    auto frelax = [&](bool have) {
+        for (int sw = 0; sw < h->o.f_sweeps; ++sw) {
+            if (lv.ff) {
+                AmgLevel &f0 = lv.ff->lev[0];
+                T *rF = P_<T>::r(f0), *dF = P_<T>::x(f0);
+                if (!have) {
+                    launch_gather<T>(lv.nF, lv.flist, r, rF, s);
+                    P_<T>::fill(e, lv.n, s);
+                    acct(h, 4.0 * nF + 2.0 * S * nF + S * n);
+                    have = true;
+                } else {
+                    launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, rF, s);
+                    acct(h, afb + 2.0 * S * nF);
+                }
+                amg_cycle<T>(h, *lv.ff, 0, rF, dF);
+                launch_scatter_add<T>(lv.nF, lv.flist, dF, e, s);
+                acct(h, 4.0 * nF + 3.0 * S * nF);
+            } else if (!have) {
+                launch_frelax_first<T>(lv.n, lv.fmap, dinv, r, e, s);
+                acct(h, 4.0 * n + S * nF + 2.0 * S * n);
+                have = true;
+            } else if (lv.aff_diag) {
+                launch_frelax_inplace<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, dinv, r, e, s);
+                acct(h, afb + 3.0 * S * nF);
+            } else {
+                launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, t, s);
+                launch_frelax_scatter<T>(lv.nF, lv.flist, dinv, t, e, s);
+                acct(h, afb + 2.0 * S * nF + 4.0 * nF + 4.0 * S * nF);
+            }
+        }
+        return have;
+    };
+    const bool global = l == 0 && h->o.global_relax;
+    const double gbytes = (double)h->bs * h->bs * S * h->ncell + 2.0 * S * n;
+    if (h->o.cycle_post) {
+        // eq. MGR-post: coarse-grid correction from e = 0, then the smoother in the
+        // reverse order of the pre-smoothing steps (F-relaxation, global relaxation)
+        csr<T>(h, 0, lv.R, P_<T>::v(lv.R), r, nullptr, nullptr, rc);
+        mgr_cycle<T>(h, l + 1, rc, ec);
+        csr<T>(h, 0, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
+        frelax(true);
+        if (global) {
+            fine_op<T>(h, 1, e, r, t);
+            launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), t, e, true, s);
+            acct(h, gbytes + S * n);
+        }
+        return;
+    }
+    // (1) global relaxation with the cell blocks (level 0)
+    bool have = false;
+    if (global) {
+        launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), r, e, false, s);
+        acct(h, gbytes);
+        have = true;
+    }
+    // (2) F-relaxation
+    have = frelax(have);
+    if (!have) {
+        P_<T>::fill(e, lv.n, s);
+        acct(h, S * n);
+    }
+    // (3) coarse-grid correction e += P M_c^{-1} R (r - A e)
+    if (l == 0) fine_op<T>(h, 1, e, r, t);
+    else csr<T>(h, 1, lv.A, Av, e, r, nullptr, t);
     csr<T>(h, 0, lv.R, P_<T>::v(lv.R), t, nullptr, nullptr, rc);
     mgr_cycle<T>(h, l + 1, rc, ec);
     csr<T>(h, 2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
@@ -785,6 +807,7 @@ int check_options(const mgr_options *o, std::string &why) {
     else if (o->frelax_amg_mask < 0) why = "frelax_amg_mask must be >= 0";
     else if (o->frelax_amg_pre < 0 || o->frelax_amg_pre > 8 || o->frelax_amg_post < 0 || o->frelax_amg_post > 8)
         why = "frelax_amg_pre/post in [0, 8]";
+    else if (o->cycle_post != 0 && o->cycle_post != 1) why = "cycle_post must be 0 or 1";
     else return MGR_OK;
     return MGR_E_INVALID;
 }
@@ -972,6 +995,7 @@ void mgr_default_options(mgr_options *o) {
     o->frelax_amg_mask = 0;
     o->frelax_amg_pre = 1;
     o->frelax_amg_post = 1;
+    o->cycle_post = 0;
 }
 
 int mgr_setup(const mgr_csr *A, int block_size, const int32_t *cf_labels, const mgr_options *opts,

@@ -213,8 +213,9 @@ void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, 
 template <typename T>
 void launch_csr_rows_residual(const DCsr &A, int lanes, const T *vals, int64_t nrows, const int32_t *rows, const T *e,
                               const T *r, T *t, hipStream_t s);
+// e = B^{-1} r with the cell-block inverses (add: e += B^{-1} r)
 template <typename T>
-void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, hipStream_t s);
+void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, bool add, hipStream_t s);
 template <typename T>
 void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T *r, T *e, hipStream_t s);
 template <typename T>

@@ -21,11 +21,11 @@ def test_fine_spmv_bitwise(orc):
         g.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_vcycle_matches_oracle(orc, precision):
+@pytest.mark.parametrize("precision,post", [("fp64", 0), ("mixed", 0), ("fp64", 1), ("mixed", 1)])
+def test_vcycle_matches_oracle(orc, precision, post):
     s = small_system((29, 23), seed=12, sigma=2.0, frac=0.35)
-    o = orc.Oracle(oracle_csr(orc, s), s.labels, precision=1 if precision == "mixed" else 0)
-    g = gpu_solver(s, precision=precision)
+    o = orc.Oracle(oracle_csr(orc, s), s.labels, precision=1 if precision == "mixed" else 0, cycle_post=post)
+    g = gpu_solver(s, precision=precision, cycle_post=post)
     r = random_vector(s.n, 1)
     z = g.apply_preconditioner(r).cpu().numpy()
     ze = o.vcycle(r)
@@ -87,7 +87,9 @@ def test_residual_history_monotone():
                                   dict(f_sweeps=2), dict(amg_pre=1, amg_post=3), dict(amg_pre=0, amg_post=1),
                                   dict(restart=1, max_iter=2000), dict(restart=64), dict(frelax_amg_mask=2),
                                   dict(frelax_amg_mask=2, f_sweeps=2, global_relax=0),
-                                  dict(frelax_amg_mask=3, precision="mixed")])
+                                  dict(frelax_amg_mask=3, precision="mixed"), dict(cycle_post=1),
+                                  dict(cycle_post=1, frelax_amg_mask=2, f_sweeps=2),
+                                  dict(cycle_post=1, rp_type=1, precision="mixed")])
 def test_option_variants_match_oracle(orc, opts):
     s = small_system((19, 17), seed=6)
     A = oracle_csr(orc, s)

@@ -107,9 +107,11 @@ def test_two_level_ideal_operators_are_exact(orc, transpose):
     assert r.status == 0 and r.iterations == 1
 
 
-def _mgr_minv(orc, o, bs_inv):
+def _mgr_minv(orc, o, bs_inv, post=False):
     """M^{-1} of the recursive MGR V-cycle from the paper's propagator
-    I - M_l^{-1} A_l = (I - P_l M_{l+1}^{-1} R_l A_l)(I - Q_l D_l^{-1} Q_l^T A_l)(I - B^{-1} A_0 at l = 0),
+    I - M_l^{-1} A_l = (I - P_l M_{l+1}^{-1} R_l A_l)(I - Q_l D_l^{-1} Q_l^T A_l)(I - B^{-1} A_0 at l = 0)
+    (eq. MGR-pre), or with post=True the reversed product of eq. MGR-post
+    (I - B^{-1} A_0 at l = 0)(I - Q_l D_l^{-1} Q_l^T A_l)(I - P_l M_{l+1}^{-1} R_l A_l),
     with AMG V(2,2) (or dense LU) below the last level."""
     L = o.n_mgr_levels
     nl = o.n_amg_levels
@@ -134,25 +136,25 @@ def _mgr_minv(orc, o, bs_inv):
         F = lv["flist"]
         Q = np.zeros((n, len(F)))
         Q[F, np.arange(len(F))] = 1
-        E = (np.eye(n) - dense(orc, lv["P"]) @ mgr_minv(l + 1) @ dense(orc, lv["R"]) @ Al) @ \
-            (np.eye(n) - Q @ np.diag(lv["dinv"]) @ Q.T @ Al)
-        if l == 0:
-            E = E @ (np.eye(n) - bs_inv @ Al)
+        Ec = np.eye(n) - dense(orc, lv["P"]) @ mgr_minv(l + 1) @ dense(orc, lv["R"]) @ Al
+        Ef = np.eye(n) - Q @ np.diag(lv["dinv"]) @ Q.T @ Al
+        Eg = np.eye(n) - bs_inv @ Al if l == 0 else np.eye(n)
+        E = Eg @ Ef @ Ec if post else Ec @ Ef @ Eg
         return (np.eye(n) - E) @ np.linalg.inv(Al)
 
     return mgr_minv(0)
 
 
-@pytest.mark.parametrize("grid", [(4, 4), (9, 9)])
-def test_vcycle_equals_closed_form_propagator(orc, grid):
+@pytest.mark.parametrize("grid,post", [((4, 4), False), ((9, 9), False), ((4, 4), True), ((9, 9), True)])
+def test_vcycle_equals_closed_form_propagator(orc, grid, post):
     s = make_system(grid, 1.0, "disk", 0.4, seed=2)
     A = orc.as_csr(s.indptr, s.indices, s.data)
-    o = orc.Oracle(A, s.labels)
+    o = orc.Oracle(A, s.labels, cycle_post=int(post))
     binv = o.block_inverses().reshape(-1, 3, 3)
     B = np.zeros((s.n, s.n))
     for c in range(s.n_cells):
         B[3 * c:3 * c + 3, 3 * c:3 * c + 3] = binv[c]
-    Minv = _mgr_minv(orc, o, B)
+    Minv = _mgr_minv(orc, o, B, post=post)
     cols = np.stack([o.vcycle(e) for e in np.eye(s.n)], axis=1)
     np.testing.assert_allclose(cols, Minv, rtol=1e-9, atol=1e-11 * np.abs(Minv).max())
 
