@@ -181,3 +181,29 @@ def test_amg_frelaxation_solve_matched_iterations(orc):
     xm, _ = gm.solve(s.b, 0.0)
     assert np.linalg.norm(xm.cpu().numpy() - ro.x) / np.linalg.norm(ro.x) <= 1e-8
     gm.close()
+
+
+def test_kernel_timing_counts_and_bytes():
+    # kernel 0: every level-0 sliced-ELL launch; kernel 1: every preconditioner application
+    s = make_config(1)
+    g = gpu_solver(s)
+    g.set_kernel_timing(True)
+    x, info = g.solve(s.b, 1e-8)
+    ms0, n0, b0 = g.kernel_time(0)
+    ms1, n1, b1 = g.kernel_time(1)
+    assert n1 == info.iterations
+    # per Arnoldi step one product w = A z and one level-0 residual inside the V-cycle,
+    # plus one true residual per restart cycle
+    cycles = -(-info.iterations // 30)
+    assert n0 == 2 * info.iterations + cycles + 1
+    assert ms0 > 0 and ms1 > 0
+    nnz, n = len(s.data), s.n
+    per0 = b0 / n0
+    assert 12 * nnz + 4 * (n + 1) + 16 * n <= per0 <= 12 * nnz + 4 * (n + 1) + 24 * n
+    # a V-cycle reads the level-0 matrix at least once
+    assert b1 / n1 > 12 * nnz
+    # counters reset after reading
+    assert g.kernel_time(1)[1] == 0
+    with pytest.raises(Exception):
+        g.kernel_time(2)
+    g.close()
