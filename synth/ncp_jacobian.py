@@ -52,6 +52,7 @@ class NCPSystem:
     labels: np.ndarray      # int32, n
     two_phase: np.ndarray   # bool, n_cells
     obs_cells: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    henry: np.ndarray = field(default_factory=lambda: np.zeros(0))  # H per cell (S-row p coefficient)
 
     @property
     def n(self) -> int:
@@ -220,7 +221,7 @@ def make_system(grid, sigma, region, frac, seed, n_obs=0, smoothing_passes=3) ->
     labels[2::3] = np.where(two, 2, 0)
     return NCPSystem(grid=grid, n_cells=N, indptr=indptr, indices=indices, data=data,
                      b=np.ascontiguousarray(b), x_true=x_true, labels=labels, two_phase=two,
-                     obs_cells=obs)
+                     obs_cells=obs, henry=H)
 
 
 def make_config(cfg: int) -> NCPSystem:
