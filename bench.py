@@ -153,6 +153,41 @@ def measured_traffic(path, cfg):
     return float(fields["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
 
 
+def run_newton(dev, cfg, steps, warmup):
+    """The semi-smooth Newton outer loop (Section 3.1) on the synthetic
+    complementarity problem at config `cfg`'s grid, started from the solution of a
+    smaller two-phase region (the previous state): one step = the whole Newton
+    solve (residual, active set, Jacobian, MGR setup + solve per Newton step)."""
+    import torch
+
+    from paper_1801_08464_amd.newton import NCPNewton
+    from synth import CONFIGS, make_ncp_problem
+    p = CONFIGS[cfg]
+    pr = make_ncp_problem(p["grid"], p["sigma"], p["region"], p["frac"], p["seed"])
+    prev = make_ncp_problem(p["grid"], p["sigma"], p["region"], 0.8 * p["frac"], p["seed"])
+    solver = NCPNewton(pr.l_indptr, pr.l_indices, pr.l_data, pr.henry, pr.f, device=dev)
+    u0 = torch.as_tensor(prev.u_star, device=dev)
+    for _ in range(warmup):
+        solver.solve(u0=u0, **SOLVER_OPTS)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = solver.solve(u0=u0, **SOLVER_OPTS)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    err = float(torch.linalg.norm(res.u - torch.as_tensor(pr.u_star, device=dev)) /
+                torch.linalg.norm(torch.as_tensor(pr.u_star, device=dev)))
+    log(f"newton: {len(res.steps) - 1} Newton steps, {dt * 1e3:.1f} ms per solve, error vs u* {err:.1e}")
+    return dict(ms_per_step=1e3 * dt, unknowns_per_s=pr.n / dt, newton_steps=len(res.steps) - 1,
+                converged=res.converged, rel_error_vs_u_star=err,
+                linear_iterations=[s.lin_iterations for s in res.steps[1:]],
+                active_cells=[s.nactive for s in res.steps],
+                setup_ms=sum(s.setup_ms for s in res.steps), solve_ms=sum(s.solve_ms for s in res.steps),
+                workload=f"config {cfg} grid {'x'.join(map(str, p['grid']))} ({pr.n} unknowns): semi-smooth Newton "
+                         f"from the state of a two-phase region of {0.8 * p['frac']:.0%} to {p['frac']:.0%}; "
+                         "step = the whole Newton solve")
+
+
 def cpu_baseline(cfg):
     """The oracle (plain C, one thread) on one eighth of the workload: the same
     generator and parameters at 64^3 cells."""
@@ -225,7 +260,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--forms", default="fp64,mixed,adjoint")
+    ap.add_argument("--forms", default="fp64,mixed,adjoint,newton")
+    ap.add_argument("--newton-config", type=int, default=3)
     ap.add_argument("--adjoint-config", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=None,
@@ -271,6 +307,8 @@ def main():
                                       f"cells ({s5.n} unknowns); loss = sum of p over {len(s5.obs_cells)} cells; step = " \
                                       "setup on A^T + adjoint solve + pattern scatter"
             del s5
+        elif form == "newton":
+            forms[form] = run_newton(dev, args.newton_config, args.steps, args.warmup)
         else:
             forms[form] = run_form(s, dev, form, args.steps, args.warmup, args.tol, timing=True)
     main_form = forms.get("fp64") or next(iter(forms.values()))
@@ -304,7 +342,7 @@ def main():
         "roofline": roof,
         "vcycle_hbm": {k: {"achieved_GBs": v["vcycle"]["achieved_GBs"], "frac": v["vcycle"]["frac_of_hbm_peak"],
                            "avg_us": v["vcycle"]["avg_us"], "bytes_per_apply": v["vcycle"]["bytes_per_launch"]}
-                       for k, v in forms.items() if "vcycle" in v and k != "adjoint"},
+                       for k, v in forms.items() if "vcycle" in v and k not in ("adjoint", "newton")},
         "forms": forms,
     }
     if not args.no_cpu_baseline:

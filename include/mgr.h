@@ -190,6 +190,36 @@ int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len);
 int mgr_set_kernel_timing(mgr_handle *h, int on);
 int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launches, double *bytes_total);
 
+/*
+ * Semi-smooth Newton support (Section 3.1, algorithm "Semi-smooth Newton Method")
+ * for the complementarity system with block_size 3: unknowns u = (p, rho, S) per
+ * cell, u[3c + v].  L (device CSR, n = 3 N rows, int32 indices, FP64 values) holds
+ * the two PDE rows of each cell (the residual H(u) = L u - f is linear in u);
+ * entries of L in the S rows are ignored.  henry: N values H_c.  The constraint of
+ * cell c is Theta_c = min(F_c, G_c), F_c = S_c, G_c = rho_c - H_c p_c.
+ *
+ * mgr_ncp_eval: if du != NULL, first u += alpha du (step 4); then R = [L u - f on
+ * the PDE rows; min(F, G) on the S rows] (step 1's residual) and labels for
+ * mgr_setup: 3 for p, 1 for rho, and for S 2 on the active set A = {F >= G}
+ * (the gas-present rows, zero diagonal) and 0 off it (the three-stage reduction of
+ * Section 5).  *rnorm = ||R||_2, *nactive = |A| (host outputs, may be NULL).  All
+ * arrays are caller-owned device memory of length n (henry: N); ordered on stream
+ * (a hipStream_t); synchronises before returning.  Errors: MGR_E_INVALID (bad CSR
+ * or null array), MGR_E_BREAKDOWN (non-finite residual), MGR_E_HIP, MGR_E_OOM.
+ *
+ * mgr_ncp_jacobian: the generalised Jacobian of step 2 for the given labels: the
+ * rows of L, and per cell the constraint row [-H_c, 1] at (p, rho) if its S label
+ * is 2, [1] at S otherwise, columns ascending.  Writes row_ptr (n + 1, device),
+ * col_idx / values (device, capacity entries) and *nnz (host).  If the Jacobian
+ * needs more than capacity entries, returns MGR_E_INVALID with *nnz set and
+ * row_ptr written, col_idx / values untouched; capacity nnz(L) + 2 N always
+ * suffices.  Ordered on stream; synchronises before returning.
+ */
+int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double *u, const double *du, double alpha,
+                 double *R, int32_t *labels, double *rnorm, int64_t *nactive, void *stream);
+int mgr_ncp_jacobian(const mgr_csr *L, const double *henry, const int32_t *labels, int32_t *row_ptr,
+                     int32_t *col_idx, double *values, int64_t capacity, int64_t *nnz, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

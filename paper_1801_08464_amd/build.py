@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["k_util.hip", "k_setup.hip", "k_fine.hip", "k_solve.hip", "k_krylov.hip", "mgr_host.hip"]
+SOURCES = ["k_util.hip", "k_setup.hip", "k_fine.hip", "k_solve.hip", "k_krylov.hip", "k_ncp.hip", "mgr_host.hip"]
 LIB = os.path.join(HERE, "libmgr.so")
 ARCH = os.environ.get("MGR_OFFLOAD_ARCH", "gfx950")
 

@@ -1178,6 +1178,73 @@ int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len) 
     }
 }
 
+static int check_ncp_csr(const mgr_csr *L) {
+    if (!L || L->n <= 0 || L->n % 3 != 0 || L->nnz < 0 || !L->row_ptr || (L->nnz > 0 && (!L->col_idx || !L->values))) {
+        g_err = "L must be a CSR with 3 rows per cell";
+        return MGR_E_INVALID;
+    }
+    return MGR_OK;
+}
+
+int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double *u, const double *du, double alpha,
+                 double *R, int32_t *labels, double *rnorm, int64_t *nactive, void *stream) {
+    if (check_ncp_csr(L) != MGR_OK) return MGR_E_INVALID;
+    if (!henry || !f || !u || !R || !labels) {
+        g_err = "null argument";
+        return MGR_E_INVALID;
+    }
+    mgr_handle t;
+    t.stream = (hipStream_t)stream;
+    mgr_handle *h = &t;
+    try {
+        const int64_t n = L->n, ncell = n / 3;
+        if (du) launch_axpy_inplace(n, alpha, du, u, h->stream);
+        Tmp<int> cnt(h, 1);
+        launch_fill_i32(cnt.p, 0, 1, h->stream);
+        launch_ncp_eval(ncell, L->row_ptr, L->col_idx, L->values, henry, f, u, R, labels, cnt.p, h->stream);
+        Tmp<double> part(h, kRedBlocks + 1);
+        launch_norm_part(n, R, part.p, h->stream);
+        launch_norm_fin(red_blocks(n), part.p, part.p + kRedBlocks, h->stream);
+        double rn = 0.0;
+        int na = 0;
+        HIPCHK(hipMemcpyAsync(&rn, part.p + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(&na, cnt.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        sync(h);
+        if (rnorm) *rnorm = rn;
+        if (nactive) *nactive = na;
+        return std::isfinite(rn) ? MGR_OK : MGR_E_BREAKDOWN;
+    } catch (const Fail &e) {
+        return e.code;
+    }
+}
+
+int mgr_ncp_jacobian(const mgr_csr *L, const double *henry, const int32_t *labels, int32_t *row_ptr,
+                     int32_t *col_idx, double *values, int64_t capacity, int64_t *nnz, void *stream) {
+    if (check_ncp_csr(L) != MGR_OK) return MGR_E_INVALID;
+    if (!henry || !labels || !row_ptr || !col_idx || !values) {
+        g_err = "null argument";
+        return MGR_E_INVALID;
+    }
+    mgr_handle t;
+    t.stream = (hipStream_t)stream;
+    mgr_handle *h = &t;
+    try {
+        const int64_t n = L->n;
+        Tmp<int32_t> cnt(h, n);
+        launch_ncp_jac_count(n, L->row_ptr, labels, cnt.p, h->stream);
+        const int64_t total = scan(h, cnt.p, row_ptr, n);
+        if (nnz) *nnz = total;
+        if (total > capacity) throw_err(h, MGR_E_INVALID, "Jacobian needs " + std::to_string(total) +
+                                                              " entries, capacity " + std::to_string(capacity));
+        launch_ncp_jac_fill(n, L->row_ptr, L->col_idx, L->values, henry, labels, row_ptr, col_idx, values,
+                            h->stream);
+        sync(h);
+        return MGR_OK;
+    } catch (const Fail &e) {
+        return e.code;
+    }
+}
+
 int mgr_set_kernel_timing(mgr_handle *h, int on) {
     if (!h) return MGR_E_INVALID;
     h->timing = on != 0;

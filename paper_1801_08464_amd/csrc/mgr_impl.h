@@ -234,6 +234,14 @@ void launch_scatter_add(int64_t n, const int32_t *idx, const T *d, T *e, hipStre
 template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s);
 
+// ---- semi-smooth Newton support (k_ncp.hip) ----
+void launch_axpy_inplace(int64_t n, double alpha, const double *du, double *u, hipStream_t s);
+void launch_ncp_eval(int64_t ncell, const int32_t *rp, const int32_t *ci, const double *v, const double *henry,
+                     const double *f, const double *u, double *R, int32_t *labels, int *nactive, hipStream_t s);
+void launch_ncp_jac_count(int64_t n, const int32_t *rp, const int32_t *labels, int32_t *cnt, hipStream_t s);
+void launch_ncp_jac_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const double *henry,
+                         const int32_t *labels, const int32_t *Jrp, int32_t *Jci, double *Jv, hipStream_t s);
+
 // ---- Krylov kernels (k_krylov.hip) ----
 // The Arnoldi basis V and w are stored with a stride ld: a multiple of 64 elements
 // with zero padding beyond n, so that every vector starts 512-byte aligned and the
