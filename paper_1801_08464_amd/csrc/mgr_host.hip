@@ -44,31 +44,78 @@ T *dalloc(mgr_handle *h, int64_t n) {
     return p;
 }
 
-// temporary device buffer released at scope exit; the release is stream-ordered,
-// so kernels already queued on the stream may still use it
+// Arenas: bump allocation in chunks taken from the stream-ordered pool.  Each
+// pool call costs tens of microseconds, and a hierarchy needs hundreds of
+// buffers, so buffers are carved out of 64 MiB chunks (a larger request gets a
+// chunk of its own) and released chunk by chunk.  Reuse is stream-ordered: a
+// kernel queued later on the stream runs after every earlier reader.
+constexpr size_t kArenaChunk = size_t(64) << 20;
+constexpr size_t kArenaAlign = 256;
+
+void *arena_alloc(mgr_handle *h, mgr_handle::Arena &a, size_t bytes) {
+    bytes = (bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+    if (bytes == 0) bytes = kArenaAlign;
+    if (bytes > kArenaChunk / 4) {
+        void *p = nullptr;
+        if (pool_alloc(h, &p, bytes) != MGR_OK) throw_err(h, MGR_E_OOM, "device allocation failed");
+        a.chunks.push_back(p);
+        return p;
+    }
+    if (bytes > a.left) {
+        void *p = nullptr;
+        if (pool_alloc(h, &p, kArenaChunk) != MGR_OK) throw_err(h, MGR_E_OOM, "device allocation failed");
+        a.chunks.push_back(p);
+        a.cur = static_cast<char *>(p);
+        a.left = kArenaChunk;
+    }
+    void *r = a.cur;
+    a.cur += bytes;
+    a.left -= bytes;
+    return r;
+}
+
+struct ArenaMark {
+    size_t nchunks;
+    char *cur;
+    size_t left;
+};
+
+ArenaMark arena_mark(const mgr_handle::Arena &a) { return {a.chunks.size(), a.cur, a.left}; }
+
+// release every chunk taken after mark m and resume bump allocation where m was
+void arena_reset(mgr_handle *h, mgr_handle::Arena &a, const ArenaMark &m) {
+    for (size_t i = m.nchunks; i < a.chunks.size(); ++i) (void)hipFreeAsync(a.chunks[i], h->stream);
+    a.chunks.resize(m.nchunks);
+    a.cur = m.cur;
+    a.left = m.left;
+}
+
+void arena_release(mgr_handle *h, mgr_handle::Arena &a) { arena_reset(h, a, ArenaMark{0, nullptr, 0}); }
+
+// the scratch temporaries of one scope, released when the scope ends
+struct ScratchScope {
+    mgr_handle *h;
+    ArenaMark m;
+    explicit ScratchScope(mgr_handle *hh) : h(hh), m(arena_mark(hh->scratch)) {}
+    ~ScratchScope() { arena_reset(h, h->scratch, m); }
+    ScratchScope(const ScratchScope &) = delete;
+    ScratchScope &operator=(const ScratchScope &) = delete;
+};
+
+// temporary device buffer in the scratch arena
 template <typename T>
 struct Tmp {
     T *p = nullptr;
-    hipStream_t s = nullptr;
-    Tmp(mgr_handle *h, int64_t n) : s(h->stream) {
-        if (pool_alloc(h, reinterpret_cast<void **>(&p), (size_t)(n > 0 ? n : 1) * sizeof(T)) != MGR_OK) {
-            p = nullptr;
-            throw_err(h, MGR_E_OOM, "device allocation failed (temporary)");
-        }
-    }
-    ~Tmp() {
-        if (p) (void)hipFreeAsync(p, s);
+    Tmp(mgr_handle *h, int64_t n) {
+        p = static_cast<T *>(arena_alloc(h, h->scratch, (size_t)(n > 0 ? n : 1) * sizeof(T)));
     }
     Tmp(const Tmp &) = delete;
     Tmp &operator=(const Tmp &) = delete;
 };
 
-// release a handle-owned buffer before the handle ends (stream-ordered)
-void release(mgr_handle *h, void *p) {
-    if (!p) return;
-    (void)hipFreeAsync(p, h->stream);
-    for (auto &q : h->allocs)
-        if (q == p) q = nullptr;
+template <typename T>
+T *salloc(mgr_handle *h, int64_t n) {
+    return static_cast<T *>(arena_alloc(h, h->scratch, (size_t)(n > 0 ? n : 1) * sizeof(T)));
 }
 
 template <typename T>
@@ -110,7 +157,7 @@ int choose_lanes(const DCsr &A) {
     return 32;
 }
 
-DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B) {
+DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     DCsr C;
     C.nrows = A.nrows;
     C.ncols = B.ncols;
@@ -127,27 +174,27 @@ DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B) {
     reset_err(h);
     launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
                   h->stream);
-    C.rp = dalloc<int32_t>(h, A.nrows + 1);
+    C.rp = scratch ? salloc<int32_t>(h, A.nrows + 1) : dalloc<int32_t>(h, A.nrows + 1);
     C.nnz = scan(h, cnt.p, C.rp, A.nrows);
     read_err(h);
     if (h->herr[6]) throw_err(h, MGR_E_INVALID, "SpGEMM: row length check failed");
-    C.ci = dalloc<int32_t>(h, C.nnz);
-    C.v = dalloc<double>(h, C.nnz);
+    C.ci = scratch ? salloc<int32_t>(h, C.nnz) : dalloc<int32_t>(h, C.nnz);
+    C.v = scratch ? salloc<double>(h, C.nnz) : dalloc<double>(h, C.nnz);
     launch_spgemm(1, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v, h->derr + 6, h->stream);
     return C;
 }
 
-DCsr transpose(mgr_handle *h, const DCsr &A, bool values) {
+DCsr transpose(mgr_handle *h, const DCsr &A, bool values, bool scratch = false) {
     DCsr T;
     T.nrows = A.ncols;
     T.ncols = A.nrows;
     Tmp<int32_t> cnt(h, A.ncols);
     launch_fill_i32(cnt.p, 0, A.ncols, h->stream);
     launch_transpose_count(A.nrows, A.rp, A.ci, cnt.p, h->stream);
-    T.rp = dalloc<int32_t>(h, A.ncols + 1);
+    T.rp = scratch ? salloc<int32_t>(h, A.ncols + 1) : dalloc<int32_t>(h, A.ncols + 1);
     T.nnz = scan(h, cnt.p, T.rp, A.ncols);
-    T.ci = dalloc<int32_t>(h, T.nnz);
-    if (values) T.v = dalloc<double>(h, T.nnz);
+    T.ci = scratch ? salloc<int32_t>(h, T.nnz) : dalloc<int32_t>(h, T.nnz);
+    if (values) T.v = scratch ? salloc<double>(h, T.nnz) : dalloc<double>(h, T.nnz);
     HIPCHK(hipMemcpyAsync(cnt.p, T.rp, A.ncols * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
     launch_transpose_fill(A.nrows, A.rp, A.ci, values ? A.v : nullptr, cnt.p, T.ci, T.v, h->stream);
     launch_transpose_sort(A.ncols, T.rp, T.ci, T.v, h->stream);
@@ -183,6 +230,7 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     const DCsr &A = lv.A;
     const int64_t n = A.nrows;
     lv.n = n;
+    ScratchScope scope(h);
     Tmp<int32_t> isF(h, n), isC(h, n), fpos(h, n + 1), cpos(h, n + 1), cmap(h, n);
     launch_level_flags(n, lv.lab, l, isF.p, isC.p, h->stream);
     lv.nF = scan(h, isF.p, fpos.p, n);
@@ -260,11 +308,8 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     }
     // A_{l+1} = R (A P)
     {
-        DCsr T = spgemm(h, A, lv.P);
+        DCsr T = spgemm(h, A, lv.P, true);
         Anext = spgemm(h, lv.R, T);
-        release(h, T.rp);
-        release(h, T.ci);
-        release(h, T.v);
     }
     lab_next = dalloc<int32_t>(h, lv.nC);
     glob_next = dalloc<int32_t>(h, lv.nC);
@@ -285,6 +330,7 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
         lv.A = A;
         lv.n = A.nrows;
         const int64_t n = A.nrows;
+        ScratchScope scope(h);
         bool coarsest = n <= o.amg_coarse_max || k == o.amg_max_levels - 1;
         if (!coarsest) {
             // strength of connection
@@ -297,7 +343,7 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
             lv.S.nnz = scan(h, cnt.p, lv.S.rp, n);
             lv.S.ci = dalloc<int32_t>(h, lv.S.nnz);
             launch_strength(1, n, A.rp, A.ci, A.v, o.amg_theta, lv.S.rp, lv.S.ci, sflag.p, h->stream);
-            DCsr ST = transpose(h, lv.S, false);
+            DCsr ST = transpose(h, lv.S, false, true);
             // PMIS
             lv.cf = dalloc<int32_t>(h, n);
             Tmp<int32_t> newc(h, n);
@@ -310,8 +356,6 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
                 if (h->herr[6] == 0) break;
                 if (h->herr[7] == 0 || round > 100000) throw_err(h, MGR_E_INVALID, "PMIS made no progress");
             }
-            release(h, ST.rp);
-            release(h, ST.ci);
             Tmp<int32_t> isC(h, n), cmap(h, n + 1);
             launch_cf_flags(n, lv.cf, isC.p, h->stream);
             const int64_t nc = scan(h, isC.p, cmap.p, n);
@@ -328,11 +372,8 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
                 lv.P.v = dalloc<double>(h, lv.P.nnz);
                 launch_interp_fill(n, A.rp, A.ci, A.v, sflag.p, lv.cf, cmap.p, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
                 lv.PT = transpose(h, lv.P, true);
-                DCsr T = spgemm(h, A, lv.P);
+                DCsr T = spgemm(h, A, lv.P, true);
                 DCsr Ac = spgemm(h, lv.PT, T);
-                release(h, T.rp);
-                release(h, T.ci);
-                release(h, T.v);
                 lv.l1 = dalloc<double>(h, n);
                 reset_err(h);
                 launch_l1(n, A.rp, A.v, lv.l1, h->derr, h->stream);
@@ -781,15 +822,42 @@ void fill_stats(mgr_handle *h, mgr_stats *st) {
     st->n_levels = k;
 }
 
+// Small pinned host blocks for the per-handle read-back words, kept for the life
+// of the process: pinning and unpinning cost milliseconds each, far more than a
+// handle's setup would otherwise spend on them.
+constexpr size_t kPinnedBlock = 256;
+std::mutex g_pinned_mu;
+std::vector<void *> g_pinned_free;
+
+void *pinned_get(mgr_handle *h) {
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        if (!g_pinned_free.empty()) {
+            void *p = g_pinned_free.back();
+            g_pinned_free.pop_back();
+            return p;
+        }
+    }
+    void *p = nullptr;
+    HIPCHK(hipHostMalloc(&p, kPinnedBlock, hipHostMallocDefault));
+    return p;
+}
+
+void pinned_put(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    g_pinned_free.push_back(p);
+}
+
 void destroy_impl(mgr_handle *h) {
     if (!h) return;
-    for (void *p : h->allocs)
-        if (p) (void)hipFreeAsync(p, h->stream);
+    arena_release(h, h->scratch);
+    arena_release(h, h->keep);
     (void)hipStreamSynchronize(h->stream);
     for (auto &t : h->tm)
         for (auto e : t.ev) (void)hipEventDestroy(e);
-    if (h->hsc) (void)hipHostFree(h->hsc);
-    if (h->herr) (void)hipHostFree(h->herr);
+    pinned_put(h->hsc);
+    pinned_put(h->herr);
     delete h;
 }
 
@@ -841,8 +909,8 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
         h->bs = bs;
         h->ncell = Ain->n / bs;
         h->m = opts->restart;
-        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&h->herr), 8 * sizeof(int), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&h->hsc), 8 * sizeof(double), hipHostMallocDefault));
+        h->herr = static_cast<int *>(pinned_get(h));
+        h->hsc = static_cast<double *>(pinned_get(h));
         h->derr = dalloc<int>(h, 8);
         const int64_t n = Ain->n, nnz = Ain->nnz;
         // pattern and labels
@@ -913,6 +981,7 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
         h->dsc = dalloc<double>(h, Dsc::size(m));
         launch_fill_f64(h->dsc, 0.0, Dsc::size(m), h->stream);
         h->part = dalloc<double>(h, (int64_t)kRedBlocks * 66);
+        arena_release(h, h->scratch);
         sync(h);
         h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         *out = h;
@@ -965,10 +1034,13 @@ int pool_alloc(mgr_handle *h, void **p, size_t bytes) {
 }
 
 int alloc(mgr_handle *h, void **p, size_t bytes) {
-    const int rc = pool_alloc(h, p, bytes);
-    if (rc != MGR_OK) return rc;
-    h->allocs.push_back(*p);
-    return MGR_OK;
+    try {
+        *p = arena_alloc(h, h->keep, bytes);
+        return MGR_OK;
+    } catch (const Fail &f) {
+        *p = nullptr;
+        return f.code;
+    }
 }
 }  // namespace mgr
 
@@ -1196,6 +1268,7 @@ int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double 
     mgr_handle t;
     t.stream = (hipStream_t)stream;
     mgr_handle *h = &t;
+    ScratchScope scope(h);
     try {
         const int64_t n = L->n, ncell = n / 3;
         if (du) launch_axpy_inplace(n, alpha, du, u, h->stream);
@@ -1228,6 +1301,7 @@ int mgr_ncp_jacobian(const mgr_csr *L, const double *henry, const int32_t *label
     mgr_handle t;
     t.stream = (hipStream_t)stream;
     mgr_handle *h = &t;
+    ScratchScope scope(h);
     try {
         const int64_t n = L->n;
         Tmp<int32_t> cnt(h, n);

@@ -80,7 +80,14 @@ struct mgr_handle {
     int64_t n = 0, ncell = 0;
     int bs = 1, L = 0;
     std::string err;
-    std::vector<void *> allocs;
+    // device memory: `keep` holds what lives as long as the handle, `scratch` the
+    // temporaries of one call (released when the call returns)
+    struct Arena {
+        std::vector<void *> chunks;
+        char *cur = nullptr;
+        size_t left = 0;
+    };
+    Arena keep, scratch;
 
     mgr::DCsr Ain;   // the matrix as passed (pattern of mgr_pattern_outer)
     mgr::DCsr A0;    // level-0 operator (A or A^T)
@@ -118,9 +125,10 @@ struct mgr_handle {
 namespace mgr {
 
 // ---- helpers (mgr_host.cpp) ----
-// device allocation from the library's stream-ordered pool on h->stream;
-// alloc() also registers the buffer for release when the handle ends
+// device allocation from the library's stream-ordered pool on h->stream
 int pool_alloc(mgr_handle *h, void **p, size_t bytes);
+// bump allocation from the handle's arena (chunks from the pool), released as a
+// whole when the handle ends
 int alloc(mgr_handle *h, void **p, size_t bytes);
 template <typename T>
 inline int alloc_n(mgr_handle *h, T **p, int64_t n) {
