@@ -595,18 +595,17 @@ __device__ inline int find_col(const int32_t *cols, int len, int key) {
 // atil = a_ii + sum_W a_in; for k in F_i ascending: den = sum_{m in C_i} abar_km
 // (abar_km = a_km when a_km a_kk < 0, else 0); den == 0 lumps a_ik into atil,
 // otherwise num_j += (a_ik abar_kj) / den; w_ij = -((a_ij + num_j) / atil).
+constexpr int kInterpMaxC = 256;  // strong C neighbours per row held in LDS by the wavefront form
+constexpr int kInterpWaves = 4;   // rows (wavefronts) per workgroup of the wavefront form
+
 __global__ void k_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
                               const uint8_t *sflag, const int32_t *cf, const int32_t *cmap, const int32_t *Prp,
                               int32_t *Pci, double *Pv) {
     int64_t i = gtid();
     if (i >= n) return;
     int base = Prp[i], nci = Prp[i + 1] - base;
-    if (cf[i] == 1) {
-        Pci[base] = cmap[i];
-        Pv[base] = 1.0;
-        return;
-    }
-    if (nci == 0) return;
+    // C rows and rows within the wavefront kernel's limit are written there
+    if (cf[i] == 1 || nci <= kInterpMaxC) return;
     int a = rp[i], b = rp[i + 1];
     int t = 0;
     for (int p = a; p < b; ++p) {
@@ -659,6 +658,140 @@ __global__ void k_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, c
         double s = v[p] + Pv[base + t];
         Pv[base + t] = (atil == 0.0) ? 0.0 : -(s / atil);
         t++;
+    }
+}
+
+// The same interpolation with one wavefront per F row (the thread-per-row form
+// above serialises every distance-two lookup of a row in one lane).  The row's
+// strong C neighbours (ascending, at most kInterpMaxC of them), their a_ij and the
+// running num_j live in LDS.  Strong F neighbours k are taken in ascending order;
+// the lanes load row k together, find each column's place in the C list by binary
+// search, and the sums (atil over the weak entries, den over row k) walk the
+// ballot masks in ascending lane order, so every sum runs in the order above.
+// Rows with more strong C neighbours are left to k_interp_fill.
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// acc + the values of the lanes in mask, added one at a time in ascending lane order
+__device__ inline double ordered_add(double acc, unsigned long long mask, double val) {
+    while (mask) {
+        const int l = __builtin_ctzll(mask);
+        acc = acc + __shfl(val, l);
+        mask &= mask - 1;
+    }
+    return acc;
+}
+
+__global__ void __launch_bounds__(kInterpWaves * kWave) k_interp_fill_wave(
+    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ v,
+    const uint8_t *__restrict__ sflag, const int32_t *__restrict__ cf, const int32_t *__restrict__ cmap,
+    const int32_t *__restrict__ Prp, int32_t *__restrict__ Pci, double *__restrict__ Pv) {
+    __shared__ int s_cols[kInterpWaves][kInterpMaxC];
+    __shared__ double s_num[kInterpWaves][kInterpMaxC];
+    __shared__ double s_aij[kInterpWaves][kInterpMaxC];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t i = (int64_t)blockIdx.x * kInterpWaves + w;
+    if (i >= n) return;
+    const int base = Prp[i], nci = Prp[i + 1] - base;
+    if (cf[i] == 1) {
+        if (lane == 0) {
+            Pci[base] = cmap[i];
+            Pv[base] = 1.0;
+        }
+        return;
+    }
+    if (nci == 0 || nci > kInterpMaxC) return;
+    int *cols = s_cols[w];
+    double *num = s_num[w], *aij = s_aij[w];
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    const int a = rp[i], b = rp[i + 1];
+    // the strong C neighbours (ascending) and the diagonal
+    int nc = 0;
+    double aii = 0.0;
+    for (int c0 = a; c0 < b; c0 += kWave) {
+        const int p = c0 + lane;
+        const bool ok = p < b;
+        const int j = ok ? ci[p] : -1;
+        const double vv = ok ? v[p] : 0.0;
+        const bool sc = ok && sflag[p] && cf[j] == 1;
+        const unsigned long long m = __ballot(sc);
+        if (sc) {
+            const int pos = nc + __popcll(m & below);
+            cols[pos] = cmap[j];
+            aij[pos] = vv;
+            num[pos] = 0.0;
+            Pci[base + pos] = cmap[j];
+        }
+        nc += __popcll(m);
+        const unsigned long long md = __ballot(ok && j == i);
+        if (md) aii = __shfl(vv, __builtin_ctzll(md));
+    }
+    wave_sync();
+    // atil = a_ii + the weak entries, ascending
+    double atil = aii;
+    for (int c0 = a; c0 < b; c0 += kWave) {
+        const int p = c0 + lane;
+        const bool ok = p < b;
+        const bool weak = ok && ci[p] != i && !sflag[p];
+        atil = ordered_add(atil, __ballot(weak), ok ? v[p] : 0.0);
+    }
+    // the strong F neighbours k, ascending
+    for (int c0 = a; c0 < b; c0 += kWave) {
+        const int p = c0 + lane;
+        const bool ok = p < b;
+        const int j = ok ? ci[p] : -1;
+        const double vv = ok ? v[p] : 0.0;
+        unsigned long long mk = __ballot(ok && j != i && sflag[p] && cf[j] == -1);
+        while (mk) {
+            const int l = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            const int k = __shfl(j, l);
+            const double aik = __shfl(vv, l);
+            const int ka = rp[k], kb = rp[k + 1];
+            double akk = 0.0;
+            for (int d0 = ka; d0 < kb; d0 += kWave) {
+                const int q = d0 + lane;
+                const bool okq = q < kb;
+                const unsigned long long md = __ballot(okq && ci[q] == k);
+                if (md) akk = __shfl(okq ? v[q] : 0.0, __builtin_ctzll(md));
+            }
+            double den = 0.0;
+            for (int d0 = ka; d0 < kb; d0 += kWave) {
+                const int q = d0 + lane;
+                const bool okq = q < kb;
+                const int mcol = okq ? ci[q] : 0;
+                const int pos = (okq && cf[mcol] == 1) ? find_col(cols, nc, cmap[mcol]) : -1;
+                const double akm = okq ? v[q] : 0.0;
+                const double abar = (akm * akk < 0.0) ? akm : 0.0;
+                den = ordered_add(den, __ballot(pos >= 0), abar);
+            }
+            if (den == 0.0) {
+                atil = atil + aik;
+                continue;
+            }
+            for (int d0 = ka; d0 < kb; d0 += kWave) {
+                const int q = d0 + lane;
+                const bool okq = q < kb;
+                const int mcol = okq ? ci[q] : 0;
+                const int pos = (okq && cf[mcol] == 1) ? find_col(cols, nc, cmap[mcol]) : -1;
+                if (pos >= 0) {
+                    const double akm = v[q];
+                    const double abar = (akm * akk < 0.0) ? akm : 0.0;
+                    const double prod = aik * abar;
+                    num[pos] = num[pos] + prod / den;
+                }
+            }
+            wave_sync();
+        }
+    }
+    wave_sync();
+    for (int t = lane; t < nc; t += kWave) {
+        const double sum = aij[t] + num[t];
+        Pv[base + t] = (atil == 0.0) ? 0.0 : -(sum / atil);
     }
 }
 
@@ -890,7 +1023,10 @@ void launch_interp_count(int64_t n, const int32_t *rp, const int32_t *ci, const 
 void launch_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *sflag,
                         const int32_t *cf, const int32_t *cmap, const int32_t *Prp, int32_t *Pci, double *Pv,
                         hipStream_t s) {
-    if (n > 0) k_interp_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp, Pci, Pv);
+    if (n <= 0) return;
+    k_interp_fill_wave<<<nblocks(n, kInterpWaves), kInterpWaves * kWave, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp,
+                                                                                  Pci, Pv);
+    k_interp_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp, Pci, Pv);
 }
 void launch_l1(int64_t n, const int32_t *rp, const double *v, double *l1, int *err, hipStream_t s) {
     if (n > 0) k_l1<<<nblocks(n, BT), BT, 0, s>>>(n, rp, v, l1, err);
