@@ -308,7 +308,10 @@ __device__ inline int group_min_i32(int v) {
     return v;
 }
 
-// G lanes (an aligned group of the wavefront) per output row
+// G lanes (an aligned group of the wavefront) per output row.  Each lane keeps,
+// per chunk, the head column and (fill pass) the head value of its B row, loaded
+// together so a merge step waits on one load.  Output t of the row is held by
+// lane t mod G and the group writes G outputs at a time (coalesced).
 template <bool FILL, int G>
 __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__restrict__ Arp,
                                                 const int32_t *__restrict__ Aci, const double *__restrict__ Av,
@@ -328,24 +331,30 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
     const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
     const int nch = (len + G - 1) / G;
     int p[kSpgChunks], e[kSpgChunks], hd[kSpgChunks];
-    double av[kSpgChunks];
+    double av[kSpgChunks], hv[kSpgChunks];
 #pragma unroll
     for (int c = 0; c < kSpgChunks; ++c) {
         p[c] = 0;
         e[c] = 0;
         hd[c] = INT_MAX;
         av[c] = 0.0;
+        hv[c] = 0.0;
         int t = c * G + glane;
         if (c < nch && t < len) {
             int k = Aci[a0 + t];
             if (FILL) av[c] = Av[a0 + t];
             p[c] = Brp[k];
             e[c] = Brp[k + 1];
-            hd[c] = p[c] < e[c] ? Bci[p[c]] : INT_MAX;
+            if (p[c] < e[c]) {
+                hd[c] = Bci[p[c]];
+                if (FILL) hv[c] = Bv[p[c]];
+            }
         }
     }
     int out = FILL ? cnt_or_Crp[row] : 0;
     int count = 0;
+    int my_j = 0;
+    double my_v = 0.0;
     for (;;) {
         int mn = INT_MAX;
 #pragma unroll
@@ -359,7 +368,7 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
             for (int c = 0; c < kSpgChunks; ++c) {
                 if (c < nch) {
                     bool hit = hd[c] == mn;
-                    double prod = hit ? av[c] * Bv[p[c]] : 0.0;
+                    double prod = hit ? av[c] * hv[c] : 0.0;
                     unsigned long long mask = (__ballot(hit) >> gbase) & gmask;
                     while (mask) {
                         int l = __builtin_ctzll(mask);
@@ -368,9 +377,14 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
                     }
                 }
             }
-            if (glane == 0) {
-                Cci[out + count] = mn;
-                Cv[out + count] = acc;
+            const int slot = count & (G - 1);
+            if (glane == slot) {
+                my_j = mn;
+                my_v = acc;
+            }
+            if (slot == G - 1) {
+                Cci[out + count - (G - 1) + glane] = my_j;
+                Cv[out + count - (G - 1) + glane] = my_v;
             }
         }
         count++;
@@ -378,8 +392,21 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
         for (int c = 0; c < kSpgChunks; ++c) {
             if (c < nch && hd[c] == mn) {
                 p[c]++;
-                hd[c] = p[c] < e[c] ? Bci[p[c]] : INT_MAX;
+                if (p[c] < e[c]) {
+                    hd[c] = Bci[p[c]];
+                    if (FILL) hv[c] = Bv[p[c]];
+                } else {
+                    hd[c] = INT_MAX;
+                }
             }
+        }
+    }
+    if (FILL) {
+        // the last count mod G outputs
+        const int rem = count & (G - 1);
+        if (glane < rem) {
+            Cci[out + count - rem + glane] = my_j;
+            Cv[out + count - rem + glane] = my_v;
         }
     }
     if (!FILL && glane == 0) cnt_or_Crp[row] = count;
