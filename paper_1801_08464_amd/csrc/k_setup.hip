@@ -489,38 +489,64 @@ __global__ void k_transpose_sort(int64_t ncols, const int32_t *Trp, int32_t *Tci
 
 // ---------------- classical strength of connection ----------------
 // j in S_i iff j != i, m_i > 0 and -s_i a_ij >= theta m_i, s_i = sign of a_ii (+ for 0)
-template <bool FILL>
-__global__ void k_strength(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
-                           int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag) {
-    int64_t i = gtid();
-    if (i >= n) return;
-    int a = rp[i], b = rp[i + 1];
-    double d = 0.0;
-    for (int p = a; p < b; ++p)
-        if (ci[p] == i) d = v[p];
-    bool pos = d >= 0.0;
+// G lanes per row: the diagonal by ballot, m_i by a group max (exact in any
+// order), the strong entries counted by a group sum and (FILL) written in
+// ascending column order through ballot prefix counts.
+template <bool FILL, int G>
+__global__ void __launch_bounds__(256) k_strength(int64_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                  double theta, int32_t *cnt_or_Srp, int32_t *__restrict__ Sci,
+                                                  uint8_t *__restrict__ sflag) {
+    const int glane = threadIdx.x & (G - 1);
+    const int gbase = (threadIdx.x & (kWave - 1)) & ~(G - 1);
+    const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    const unsigned long long below = glane == 0 ? 0ull : ((1ull << glane) - 1);
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / G) + (threadIdx.x / G);
+    if (i >= n) return;  // uniform per group
+    const int a = rp[i], b = rp[i + 1];
+    double dl = 0.0;
+    bool has = false;
+    for (int p = a + glane; p < b; p += G)
+        if (ci[p] == i) {
+            dl = v[p];
+            has = true;
+        }
+    const unsigned long long md = (__ballot(has) >> gbase) & gmask;
+    const double d = md ? __shfl(dl, gbase + __builtin_ctzll(md)) : 0.0;
+    const bool pos = d >= 0.0;
     double m = -INFINITY;
-    for (int p = a; p < b; ++p) {
+    for (int p = a + glane; p < b; p += G) {
         if (ci[p] == i) continue;
-        double t = pos ? -v[p] : v[p];
+        const double t = pos ? -v[p] : v[p];
         if (t > m) m = t;
     }
-    double thr = theta * m;
-    int q = FILL ? cnt_or_Srp[i] : 0;
-    int cnt = 0;
-    for (int p = a; p < b; ++p) {
-        bool strong = false;
-        if (ci[p] != i && m > 0.0) {
-            double t = pos ? -v[p] : v[p];
-            strong = t >= thr;
-        }
-        if (strong) {
-            if (FILL) Sci[q + cnt] = ci[p];
-            cnt++;
-        }
-        if (FILL) sflag[p] = strong ? 1 : 0;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        const double o = __shfl_xor(m, off);
+        m = o > m ? o : m;
     }
-    if (!FILL) cnt_or_Srp[i] = cnt;
+    const double thr = theta * m;
+    const int q = FILL ? cnt_or_Srp[i] : 0;
+    int cnt = 0;
+    for (int p0 = a; p0 < b; p0 += G) {
+        const int p = p0 + glane;
+        bool strong = false;
+        int j = -1;
+        if (p < b) {
+            j = ci[p];
+            if (j != i && m > 0.0) {
+                const double t = pos ? -v[p] : v[p];
+                strong = t >= thr;
+            }
+        }
+        const unsigned long long ms = (__ballot(strong) >> gbase) & gmask;
+        if (FILL) {
+            if (strong) Sci[q + cnt + __popcll(ms & below)] = j;
+            if (p < b) sflag[p] = strong ? 1 : 0;
+        }
+        cnt += __popcll(ms);
+    }
+    if (!FILL && glane == 0) cnt_or_Srp[i] = cnt;
 }
 
 // ---------------- PMIS ----------------
@@ -1021,13 +1047,20 @@ void launch_transpose_fill(int64_t nrows, const int32_t *rp, const int32_t *ci, 
 void launch_transpose_sort(int64_t ncols, const int32_t *Trp, int32_t *Tci, double *Tv, hipStream_t s) {
     if (ncols > 0) k_transpose_sort<<<nblocks(ncols, BT), BT, 0, s>>>(ncols, Trp, Tci, Tv);
 }
-void launch_strength(int pass, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
-                     int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag, hipStream_t s) {
+template <int G>
+static void strength_g(int pass, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
+                       int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag, hipStream_t s) {
+    const unsigned g = nblocks(n, BT / G);
+    if (pass == 0) k_strength<false, G><<<g, BT, 0, s>>>(n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag);
+    else k_strength<true, G><<<g, BT, 0, s>>>(n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag);
+}
+void launch_strength(int pass, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
+                     double theta, int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag, hipStream_t s) {
     if (n <= 0) return;
-    if (pass == 0)
-        k_strength<false><<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag);
-    else
-        k_strength<true><<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag);
+    const double avg = (double)nnz / (double)n;
+    if (avg < 12) strength_g<8>(pass, n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag, s);
+    else if (avg < 32) strength_g<16>(pass, n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag, s);
+    else strength_g<32>(pass, n, rp, ci, v, theta, cnt_or_Srp, Sci, sflag, s);
 }
 void launch_pmis_init(int64_t n, const int32_t *STrp, int32_t *state, hipStream_t s) {
     if (n > 0) k_pmis_init<<<nblocks(n, BT), BT, 0, s>>>(n, STrp, state);

@@ -336,13 +336,13 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
             // strength of connection
             Tmp<int32_t> cnt(h, n);
             Tmp<uint8_t> sflag(h, A.nnz);
-            launch_strength(0, n, A.rp, A.ci, A.v, o.amg_theta, cnt.p, nullptr, nullptr, h->stream);
+            launch_strength(0, n, A.nnz, A.rp, A.ci, A.v, o.amg_theta, cnt.p, nullptr, nullptr, h->stream);
             lv.S.nrows = n;
             lv.S.ncols = n;
             lv.S.rp = dalloc<int32_t>(h, n + 1);
             lv.S.nnz = scan(h, cnt.p, lv.S.rp, n);
             lv.S.ci = dalloc<int32_t>(h, lv.S.nnz);
-            launch_strength(1, n, A.rp, A.ci, A.v, o.amg_theta, lv.S.rp, lv.S.ci, sflag.p, h->stream);
+            launch_strength(1, n, A.nnz, A.rp, A.ci, A.v, o.amg_theta, lv.S.rp, lv.S.ci, sflag.p, h->stream);
             DCsr ST = transpose(h, lv.S, false, true);
             // PMIS
             lv.cf = dalloc<int32_t>(h, n);

@@ -191,8 +191,8 @@ void launch_transpose_fill(int64_t nrows, const int32_t *rp, const int32_t *ci, 
                            int32_t *Tci, double *Tv, hipStream_t s);
 void launch_transpose_sort(int64_t ncols, const int32_t *Trp, int32_t *Tci, double *Tv, hipStream_t s);
 // classical AMG
-void launch_strength(int pass, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
-                     int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag, hipStream_t s);
+void launch_strength(int pass, int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
+                     double theta, int32_t *cnt_or_Srp, int32_t *Sci, uint8_t *sflag, hipStream_t s);
 void launch_pmis_init(int64_t n, const int32_t *STrp, int32_t *state, hipStream_t s);
 void launch_pmis_select(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *STrp, const int32_t *STci,
                         const int32_t *state, uint64_t seed, int32_t *newc, hipStream_t s);
