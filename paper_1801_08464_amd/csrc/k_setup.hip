@@ -26,7 +26,7 @@ __device__ inline double row_diag(const int32_t *rp, const int32_t *ci, const do
 __global__ void k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const int32_t *lab,
                            int *err) {
     int64_t i = gtid();
-    if (i >= n) return;
+    if (i >= n) i = n - 1;  // surplus lanes repeat the last row (idempotent), so whole wavefronts reduce
     int a = rp[i], b = rp[i + 1];
     bool bad = a < 0 || b < a || (int64_t)b > nnz;
     if (!bad) {
@@ -40,9 +40,13 @@ __global__ void k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int3
     }
     if (bad) atomicOr(&err[0], 1);
     if (lab) {
-        int L = lab[i];
+        const int L = lab[i];
         if (L < 0 || L > 31) atomicOr(&err[2], 1);
-        else atomicMax(&err[1], L);
+        // the labels present, as a bit set reduced over the wavefront: one atomic per wavefront
+        unsigned bits = (L >= 0 && L <= 31) ? (1u << L) : 0u;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) bits |= (unsigned)__shfl_xor((int)bits, o);
+        if ((threadIdx.x & (kWave - 1)) == 0 && bits) atomicMax(&err[1], 31 - __builtin_clz(bits));
     }
 }
 
@@ -594,23 +598,32 @@ __global__ void k_pmis_select(int64_t n, const int32_t *Srp, const int32_t *Sci,
 }
 
 // new C points become C; undecided points that strongly depend on a new C point become F.
-// counters[0] += undecided left, counters[1] += new C points.
+// counters[0] += undecided left, counters[1] += new C points (counted per wavefront,
+// one atomic each).
 __global__ void k_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *newc,
                               int32_t *state, int *counters) {
-    int64_t i = gtid();
-    if (i >= n) return;
-    if (newc[i]) {
-        state[i] = 1;
-        atomicAdd(&counters[1], 1);
-        return;
-    }
-    if (state[i] != 0) return;
-    for (int p = Srp[i]; p < Srp[i + 1]; ++p)
-        if (newc[Sci[p]]) {
-            state[i] = -1;
-            return;
+    const int64_t i = gtid();
+    bool und = false, nc = false;
+    if (i < n) {
+        if (newc[i]) {
+            state[i] = 1;
+            nc = true;
+        } else if (state[i] == 0) {
+            bool f = false;
+            for (int p = Srp[i]; p < Srp[i + 1]; ++p)
+                if (newc[Sci[p]]) {
+                    f = true;
+                    break;
+                }
+            if (f) state[i] = -1;
+            else und = true;
         }
-    atomicAdd(&counters[0], 1);
+    }
+    const int cu = __popcll(__ballot(und)), cc = __popcll(__ballot(nc));
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (cu) atomicAdd(&counters[0], cu);
+        if (cc) atomicAdd(&counters[1], cc);
+    }
 }
 
 __global__ void k_cf_flags(int64_t n, const int32_t *state, int32_t *isC) {
