@@ -57,8 +57,6 @@ def lib():
         P = C.POINTER
         L.orc_default_opts.argtypes = [P(_Opts)]
         L.orc_mat_free.argtypes = [P(_Mat)]
-        for name in ("orc_transpose", "orc_spgemm"):
-            pass
         L.orc_spmv.argtypes = [P(_Mat), C.c_void_p, C.c_void_p]
         L.orc_transpose.argtypes = [P(_Mat), P(_Mat)]
         L.orc_spgemm.argtypes = [P(_Mat), P(_Mat), P(_Mat)]
