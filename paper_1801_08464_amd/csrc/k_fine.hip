@@ -9,9 +9,12 @@ namespace {
 // Fine-level SpMV on the cell-sliced ELL: one wavefront per 64-cell slice, one
 // thread per cell computing all BS rows of its cell (so each cell's outputs are
 // written together, without partial-line writes).  Each component's slots are
-// read in chunks of 8: every column and value load of a chunk (each a contiguous
-// wavefront segment) is issued before the dependent gathers of x.  Row sums run
-// in ascending column order.
+// read in chunks of kChunk: every column and value load of a chunk (each a contiguous
+// wavefront segment) is issued before the dependent gathers of x; the matrix is
+// streamed with non-temporal loads so that it does not evict x from the caches.
+// Row sums run in ascending column order.
+constexpr int kChunk = 16;
+
 template <typename T, int MODE, int BS>
 __global__ void __launch_bounds__(256) k_csell(int64_t ncell, int64_t nslice, const int32_t *__restrict__ off,
                                                     const int32_t *__restrict__ width,
@@ -31,18 +34,18 @@ __global__ void __launch_bounds__(256) k_csell(int64_t ncell, int64_t nslice, co
         const int32_t *cp = col + o * kWave + lane;
         const T *vp = val + o * kWave + lane;
         T acc = 0;
-        for (int t0 = 0; t0 < w; t0 += 8) {
-            int j[8];
-            T a[8], xv[8];
+        for (int t0 = 0; t0 < w; t0 += kChunk) {
+            int j[kChunk];
+            T a[kChunk], xv[kChunk];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                j[u] = t0 + u < w ? cp[(int64_t)(t0 + u) * kWave] : -1;
-                a[u] = t0 + u < w ? vp[(int64_t)(t0 + u) * kWave] : (T)0;
+            for (int u = 0; u < kChunk; ++u) {
+                j[u] = t0 + u < w ? __builtin_nontemporal_load(cp + (int64_t)(t0 + u) * kWave) : -1;
+                a[u] = t0 + u < w ? __builtin_nontemporal_load(vp + (int64_t)(t0 + u) * kWave) : (T)0;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
+            for (int u = 0; u < kChunk; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
+            for (int u = 0; u < kChunk; ++u)
                 if (j[u] >= 0) acc = acc + a[u] * xv[u];
         }
         out[comp] = acc;

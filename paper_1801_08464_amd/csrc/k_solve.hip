@@ -14,28 +14,36 @@ __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + thr
 // CSR "stream" SpMV: a workgroup owns ROWS consecutive rows.  Their nonzeros are
 // read as one contiguous, coalesced stream in passes of kStreamLds entries; in a
 // pass each thread issues the column and value loads of all its entries before
-// their dependent gathers of x, and stages the products v*x in LDS.  Then thread t
+// their dependent gathers of x, and stages the products v*x in LDS (the loads of
+// pass p+1 are issued before the row sums of pass p, so they overlap).  Then thread t
 // sums row rb+t sequentially in ascending column order (a row's entries may span
 // several passes, which run in ascending order).  No padding, any row-length mix,
 // and the same summation order per row as a sequential CSR loop.  The matrix is
 // streamed with non-temporal loads so that it does not evict x from the caches.
-// Modes: 0 y = Ax; 1 y = r - Ax; 2 y += Ax; 3 y = x + (r - Ax)/d (Jacobi sweep).
+// Modes: 0 y = Ax; 1 y = r - Ax; 2 y += Ax; 3 y = x + (r - Ax)/d (Jacobi sweep);
+// 4 y = Ax and y2 = y/d (a restriction that also forms the next level's first
+// Jacobi iterate from zero, the division the separate pass would do).
 constexpr int kStreamLds = 4096;
 
 template <typename T, int MODE>
 __device__ inline void row_store(int64_t row, T acc, const T *__restrict__ x, const T *__restrict__ r,
-                                 const T *__restrict__ d, T *__restrict__ y) {
+                                 const T *__restrict__ d, T *__restrict__ y, T *__restrict__ y2) {
     if (MODE == 0) y[row] = acc;
     else if (MODE == 1) y[row] = r[row] - acc;
     else if (MODE == 2) y[row] = y[row] + acc;
-    else y[row] = x[row] + (r[row] - acc) / d[row];
+    else if (MODE == 3) y[row] = x[row] + (r[row] - acc) / d[row];
+    else {
+        y[row] = acc;
+        y2[row] = acc / d[row];
+    }
 }
 
 template <typename T, int MODE, int ROWS>
 __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci, const T *__restrict__ v,
                                                      const T *__restrict__ x, const T *__restrict__ r,
-                                                     const T *__restrict__ d, T *__restrict__ y) {
+                                                     const T *__restrict__ d, T *__restrict__ y,
+                                                     T *__restrict__ y2) {
     constexpr int LDSN = kStreamLds;
     constexpr int B = LDSN / ROWS;  // entries per thread per pass
     __shared__ T sh[LDSN];
@@ -50,16 +58,22 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
         b = rp[row + 1];
     }
     T acc = 0;
-    for (int base = p0; base < p1; base += LDSN) {
+    int j[B];
+    T av[B];
+    // the column/value loads of pass p+1 are issued before pass p's row sums
+    auto load_pass = [&](int base) {
         const int lim = base + LDSN < p1 ? base + LDSN : p1;
-        int j[B];
-        T av[B], xv[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const int p = base + u * ROWS + tid;
             j[u] = p < lim ? __builtin_nontemporal_load(ci + p) : -1;
             av[u] = p < lim ? __builtin_nontemporal_load(v + p) : (T)0;
         }
+    };
+    if (p0 < p1) load_pass(p0);
+    for (int base = p0; base < p1; base += LDSN) {
+        const int lim = base + LDSN < p1 ? base + LDSN : p1;
+        T xv[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
 #pragma unroll
@@ -68,11 +82,12 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
             if (p < lim) sh[p - base] = av[u] * xv[u];
         }
         __syncthreads();
+        if (base + LDSN < p1) load_pass(base + LDSN);
         const int lo = a > base ? a : base, hi = b < lim ? b : lim;
         for (int p = lo; p < hi; ++p) acc = acc + sh[p - base];
         __syncthreads();
     }
-    if (row < re) row_store<T, MODE>(row, acc, x, r, d, y);
+    if (row < re) row_store<T, MODE>(row, acc, x, r, d, y, y2);
 }
 
 // Row-list kernels on the compact copy of a level's F rows (row f of AF is row
@@ -126,7 +141,7 @@ template <typename T, int MODE, int LANES>
 __global__ void __launch_bounds__(256) k_csr_lanes(int64_t nrows, const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci, const T *__restrict__ v,
                                                    const T *__restrict__ x, const T *__restrict__ r,
-                                                   const T *__restrict__ d, T *__restrict__ y) {
+                                                   const T *__restrict__ d, T *__restrict__ y, T *__restrict__ y2) {
     const int64_t gid = gtid();
     const int64_t row = gid / LANES;
     const int sub = (int)(gid % LANES);
@@ -135,7 +150,7 @@ __global__ void __launch_bounds__(256) k_csr_lanes(int64_t nrows, const int32_t 
         for (int p = rp[row] + sub; p < rp[row + 1]; p += LANES) s = s + v[p] * x[ci[p]];
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
-    if (row < nrows && sub == 0) row_store<T, MODE>(row, s, x, r, d, y);
+    if (row < nrows && sub == 0) row_store<T, MODE>(row, s, x, r, d, y, y2);
 }
 
 // e = B^{-1} r per cell (ADD: e += B^{-1} r)
@@ -248,28 +263,33 @@ __global__ void __launch_bounds__(kWave) k_lu_solve_wave(int n, const double *__
 constexpr int BT = 256;
 
 template <typename T, int ROWS>
-static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y,
+static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
                      hipStream_t s) {
     const unsigned g = nblocks(A.nrows, ROWS);
+#define MGR_STREAM(M) k_csr_stream<T, M, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2)
     switch (mode) {
-    case 0: k_csr_stream<T, 0, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 1: k_csr_stream<T, 1, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 2: k_csr_stream<T, 2, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    default: k_csr_stream<T, 3, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 0: MGR_STREAM(0); break;
+    case 1: MGR_STREAM(1); break;
+    case 2: MGR_STREAM(2); break;
+    case 3: MGR_STREAM(3); break;
+    default: MGR_STREAM(4); break;
     }
+#undef MGR_STREAM
 }
 
 template <typename T, int MODE>
-static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const T *r, const T *d, T *y,
+static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
                       hipStream_t s) {
     const unsigned g = nblocks(A.nrows * lanes, BT);
+#define MGR_LANES(L) k_csr_lanes<T, MODE, L><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2)
     switch (lanes) {
-    case 2: k_csr_lanes<T, MODE, 2><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 4: k_csr_lanes<T, MODE, 4><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 8: k_csr_lanes<T, MODE, 8><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    case 16: k_csr_lanes<T, MODE, 16><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
-    default: k_csr_lanes<T, MODE, 32><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y); break;
+    case 2: MGR_LANES(2); break;
+    case 4: MGR_LANES(4); break;
+    case 8: MGR_LANES(8); break;
+    case 16: MGR_LANES(16); break;
+    default: MGR_LANES(32); break;
     }
+#undef MGR_LANES
 }
 
 // below this many rows the lanes-per-row kernel is faster (measured on the 128^3
@@ -280,20 +300,32 @@ constexpr int64_t kCsrStreamMinRows = 131072;
 // Large levels: 256-row stream workgroups (sequential row sums).  Small levels,
 // where those would leave most CUs idle: several lanes per row.
 template <typename T>
-void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
+static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
+                    hipStream_t s) {
     if (A.nrows <= 0) return;
     if (A.nrows >= kCsrStreamMinRows) {
-        csr_rows<T, 256>(mode, A, vals, x, r, d, y, s);
+        csr_rows<T, 256>(mode, A, vals, x, r, d, y, y2, s);
         return;
     }
     const double avg = (double)A.nnz / (double)A.nrows;
     const int lanes = avg < 3 ? 2 : avg < 6 ? 4 : avg < 12 ? 8 : avg < 24 ? 16 : 32;
     switch (mode) {
-    case 0: csr_lanes<T, 0>(A, lanes, vals, x, r, d, y, s); break;
-    case 1: csr_lanes<T, 1>(A, lanes, vals, x, r, d, y, s); break;
-    case 2: csr_lanes<T, 2>(A, lanes, vals, x, r, d, y, s); break;
-    default: csr_lanes<T, 3>(A, lanes, vals, x, r, d, y, s); break;
+    case 0: csr_lanes<T, 0>(A, lanes, vals, x, r, d, y, y2, s); break;
+    case 1: csr_lanes<T, 1>(A, lanes, vals, x, r, d, y, y2, s); break;
+    case 2: csr_lanes<T, 2>(A, lanes, vals, x, r, d, y, y2, s); break;
+    case 3: csr_lanes<T, 3>(A, lanes, vals, x, r, d, y, y2, s); break;
+    default: csr_lanes<T, 4>(A, lanes, vals, x, r, d, y, y2, s); break;
     }
+}
+
+template <typename T>
+void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
+    csr_any<T>(mode, A, vals, x, r, d, y, nullptr, s);
+}
+
+template <typename T>
+void launch_csr_restrict_div(const DCsr &A, const T *vals, const T *x, const T *d, T *y, T *y2, hipStream_t s) {
+    csr_any<T>(4, A, vals, x, nullptr, d, y, y2, s);
 }
 
 template <typename T>
@@ -375,6 +407,7 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
 
 #define MGR_INSTANTIATE(T)                                                                                      \
     template void launch_csr<T>(int, const DCsr &, const T *, const T *, const T *, const T *, T *, hipStream_t); \
+    template void launch_csr_restrict_div<T>(const DCsr &, const T *, const T *, const T *, T *, T *, hipStream_t); \
     template void launch_csr_rows_residual<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *, \
                                               const T *, T *, hipStream_t);                                     \
     template void launch_frelax_inplace<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *,   \

@@ -550,8 +550,10 @@ void csr(mgr_handle *h, int mode, const DCsr &A, const T *vals, const T *x, cons
     acct(h, csr_bytes(A, mode, sizeof(T)));
 }
 
+// x0_ready: the caller's restriction already wrote x0 = r / l1 (the first Jacobi
+// iterate from zero) where this level's first sweep reads it
 template <typename T>
-void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x) {
+void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready = false) {
     AmgLevel &lv = H.lev[k];
     hipStream_t s = h->stream;
     const int64_t n = lv.n;
@@ -570,8 +572,10 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x) {
     T *oth = (cur == x) ? P_<T>::x2(lv) : x;
     for (int it = 0; it < pre; ++it) {
         if (it == 0) {
-            launch_div<T>(n, r, l1, cur, s);
-            acct(h, 3.0 * S * n);
+            if (!x0_ready) {
+                launch_div<T>(n, r, l1, cur, s);
+                acct(h, 3.0 * S * n);
+            }
         } else {
             csr<T>(h, 3, lv.A, Av, cur, r, l1, oth);
             std::swap(cur, oth);
@@ -584,8 +588,16 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x) {
     T *t = P_<T>::t(lv);
     csr<T>(h, 1, lv.A, Av, cur, r, nullptr, t);
     AmgLevel &nx = H.lev[k + 1];
-    csr<T>(h, 0, lv.PT, P_<T>::v(lv.PT), t, nullptr, nullptr, P_<T>::r(nx));
-    amg_cycle<T>(h, H, k + 1, P_<T>::r(nx), P_<T>::x(nx));
+    if (pre > 0 && k + 1 < (int)H.lev.size() - 1) {
+        // restriction + the next level's x0 = r / l1, written where its first sweep reads it
+        T *nx_cur = (swaps % 2 == 0) ? P_<T>::x(nx) : P_<T>::x2(nx);
+        launch_csr_restrict_div<T>(lv.PT, P_<T>::v(lv.PT), t, P_<T>::l1(nx), P_<T>::r(nx), nx_cur, s);
+        acct(h, csr_bytes(lv.PT, 0, S) + 2.0 * S * (double)nx.n);
+        amg_cycle<T>(h, H, k + 1, P_<T>::r(nx), P_<T>::x(nx), true);
+    } else {
+        csr<T>(h, 0, lv.PT, P_<T>::v(lv.PT), t, nullptr, nullptr, P_<T>::r(nx));
+        amg_cycle<T>(h, H, k + 1, P_<T>::r(nx), P_<T>::x(nx));
+    }
     csr<T>(h, 2, lv.P, P_<T>::v(lv.P), P_<T>::x(nx), nullptr, nullptr, cur);
     for (int it = 0; it < post; ++it) {
         csr<T>(h, 3, lv.A, Av, cur, r, l1, oth);

@@ -216,6 +216,9 @@ void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *
 // mode 0: y = A x;  1: y = r - A x;  2: y += A x;  3: y = x + (r - A x) / d (x != y)
 template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s);
+// y = A x and y2 = y / d (restriction that also starts the next level's Jacobi sweeps)
+template <typename T>
+void launch_csr_restrict_div(const DCsr &A, const T *vals, const T *x, const T *d, T *y, T *y2, hipStream_t s);
 // F-row residual t[f] = r[i] - (A e)[i], i = rows[f]; A is the compact F-row copy
 // (its row f is row rows[f] of the level matrix)
 template <typename T>
