@@ -89,6 +89,7 @@ def run_form(s, dev, form, steps, warmup, tol, timing=False):
     dt = time.perf_counter() - t0
     ktime = [k.kernel_time(0) for k in keep if hasattr(k, "kernel_time")] if timing else []
     vtime = [k.kernel_time(1) for k in keep if hasattr(k, "kernel_time")] if timing else []
+    stime = [k.kernel_time(2) for k in keep if hasattr(k, "kernel_time")] if timing else []
     err = None
     if form != "adjoint":
         xt = torch.as_tensor(s.x_true, device=dev)
@@ -123,6 +124,8 @@ def run_form(s, dev, form, steps, warmup, tol, timing=False):
 
     if ktime:
         out["fine_kernel"] = summary(ktime)
+    if stime:
+        out["coarse_sweep"] = summary(stime)
     if vtime:
         v = summary(vtime)
         v["frac_of_hbm_peak"] = v["achieved_GBs"] / HBM_PEAK_GBS
@@ -130,27 +133,36 @@ def run_form(s, dev, form, steps, warmup, tol, timing=False):
     return out
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_csell_128cube_fp64_hbm_traffic.md")
-FINE_KERNEL_SOURCE = os.path.join(ROOT, "paper_1801_08464_amd", "csrc", "k_fine.hip")
+FINE_RECORD = os.path.join(ROOT, "profiles", "k_csell_128cube_fp64_hbm_traffic.md")
+FINE_SOURCE = os.path.join(ROOT, "paper_1801_08464_amd", "csrc", "k_fine.hip")
+SWEEP_RECORD = os.path.join(ROOT, "profiles", "k_csr_stream_coarse_sweep_128cube_fp64_hbm_traffic.md")
+SWEEP_SOURCE = os.path.join(ROOT, "paper_1801_08464_amd", "csrc", "k_solve.hip")
 
 
-def measured_traffic(path, cfg):
-    """HBM bytes per launch of the fine kernel from the rocprofv3 FETCH_SIZE and
+def measured_traffic(path, source, cfg):
+    """HBM bytes per launch of a kernel from its rocprofv3 FETCH_SIZE and
     WRITE_SIZE record (calibrated against a plain copy), or None when the record
     is missing, is for another workload, or the kernel source has changed since."""
     import hashlib
     import re
-    path = path or TRAFFIC_RECORD
     if not os.path.exists(path):
         return None, "no PMC record"
     txt = open(path).read()
     fields = dict(re.findall(r"^- (\w+): (\S+)", txt, re.M))
-    src = hashlib.sha256(open(FINE_KERNEL_SOURCE, "rb").read()).hexdigest()
+    src = hashlib.sha256(open(source, "rb").read()).hexdigest()
     if fields.get("source_sha256") != src:
         return None, "kernel changed since the PMC record"
     if fields.get("config") != str(cfg):
         return None, "PMC record is for another workload"
     return float(fields["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
+def roofline(rec, kernel, record, source, cfg):
+    traffic, note = measured_traffic(record, source, cfg)
+    return dict(bound="hbm", achieved=rec["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=rec["achieved_GBs"] / HBM_PEAK_GBS, traffic=traffic, kernel=kernel, avg_us=rec["avg_us"],
+                launches=rec["launches"], algorithmic_bytes_per_launch=rec["bytes_per_launch"],
+                traffic_source=note)
 
 
 def run_newton(dev, cfg, steps, warmup):
@@ -264,8 +276,6 @@ def main():
     ap.add_argument("--newton-config", type=int, default=3)
     ap.add_argument("--adjoint-config", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default=None,
-                    help="rocprofv3 FETCH_SIZE/WRITE_SIZE record of the fine kernel (default: the one under profiles/)")
     ap.add_argument("--variants", default=None,
                     help="comma-separated configs: time the R/P and cycle variants of the preconditioner "
                          "against the default on them (prints one JSON line with the table)")
@@ -314,14 +324,14 @@ def main():
     main_form = forms.get("fp64") or next(iter(forms.values()))
     p = CONFIGS[args.config]
     fk = main_form.get("fine_kernel")
-    roof = None
-    if fk:
-        traffic, traffic_note = measured_traffic(args.traffic, args.config)
-        roof = dict(bound="hbm", achieved=fk["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=fk["achieved_GBs"] / HBM_PEAK_GBS, traffic=traffic,
-                    kernel="k_csell (level-0 sliced-ELL SpMV / residual, FP64)",
-                    avg_us=fk["avg_us"], launches=fk["launches"],
-                    algorithmic_bytes_per_launch=fk["bytes_per_launch"], traffic_source=traffic_note)
+    cs = main_form.get("coarse_sweep")
+    # the dominant kernel of a step: the l1-Jacobi sweep on the coarse-grid matrix
+    # (three launches per iteration); the fine-level operator is reported beside it
+    roof = roofline(cs, "k_csr_stream<double, 3, 256>: l1-Jacobi sweep on the coarse-grid matrix "
+                        "(AMG level 0 of the pressure system)", SWEEP_RECORD, SWEEP_SOURCE,
+                    args.config) if cs else None
+    roof_fine = roofline(fk, "k_csell: level-0 sliced-ELL SpMV / residual (the GMRES operator)", FINE_RECORD,
+                         FINE_SOURCE, args.config) if fk else None
     line = {
         "metric": METRIC,
         "value": main_form["unknowns_per_s"],
@@ -340,6 +350,7 @@ def main():
                                f"{p['region']}; step = mgr_setup + mgr_solve to {args.tol:g}",
                    "restart": 30, "tol": args.tol, "seed": p["seed"]},
         "roofline": roof,
+        "roofline_fine": roof_fine,
         "vcycle_hbm": {k: {"achieved_GBs": v["vcycle"]["achieved_GBs"], "frac": v["vcycle"]["frac_of_hbm_peak"],
                            "avg_us": v["vcycle"]["avg_us"], "bytes_per_apply": v["vcycle"]["bytes_per_launch"]}
                        for k, v in forms.items() if "vcycle" in v and k not in ("adjoint", "newton")},

@@ -176,7 +176,8 @@ int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len);
 
 /*
  * Kernel timing: when on, every launch of the level-0 sliced-ELL SpMV /
- * residual kernel, and every whole preconditioner application (the MGR
+ * residual kernel, every l1-Jacobi sweep on the coarse-grid matrix (level 0 of
+ * the coarse AMG hierarchy), and every whole preconditioner application (the MGR
  * V-cycle of Section 4, algorithm "MGR preconditioner with presmoothing", inside mgr_solve or
  * mgr_apply_preconditioner), is bracketed by HIP events on the handle's stream.
  * mgr_kernel_time (synchronises) returns the summed event time, the number of
@@ -184,8 +185,10 @@ int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len);
  * counters.  kernel: 0 = the level-0 kernel (bytes: stored values and column
  * indices of the true nonzeros, row pointers, x, y and r when read); 1 = the
  * V-cycle (bytes: the sum over its launches of every array each reads or
- * writes, counted once per launch, with gathered vectors at their length).
- * Returns MGR_E_INVALID for another kernel id.
+ * writes, counted once per launch, with gathered vectors at their length);
+ * 2 = the coarse-grid sweeps (bytes: stored values and column indices, row
+ * pointers, the gathered x, and r, d and y).  Returns MGR_E_INVALID for another
+ * kernel id.
  */
 int mgr_set_kernel_timing(mgr_handle *h, int on);
 int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launches, double *bytes_total);

@@ -550,6 +550,21 @@ void csr(mgr_handle *h, int mode, const DCsr &A, const T *vals, const T *x, cons
     acct(h, csr_bytes(A, mode, sizeof(T)));
 }
 
+// a Jacobi sweep on level k of hierarchy H; the sweeps on the coarse-grid matrix
+// itself (level 0 of the coarse hierarchy) are bracketed by events when timing
+template <typename T>
+void sweep(mgr_handle *h, const AmgHier &H, int k, const DCsr &A, const T *vals, const T *x, const T *r,
+           const T *d, T *y) {
+    const bool timed = h->timing && &H == &h->cg && k == 0;
+    if (timed) timer_mark(h, h->tm[2]);
+    csr<T>(h, 3, A, vals, x, r, d, y);
+    if (timed) {
+        timer_mark(h, h->tm[2]);
+        h->tm[2].bytes += csr_bytes(A, 3, sizeof(T));
+        h->tm[2].launches++;
+    }
+}
+
 // x0_ready: the caller's restriction already wrote x0 = r / l1 (the first Jacobi
 // iterate from zero) where this level's first sweep reads it
 template <typename T>
@@ -577,7 +592,7 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready
                 acct(h, 3.0 * S * n);
             }
         } else {
-            csr<T>(h, 3, lv.A, Av, cur, r, l1, oth);
+            sweep<T>(h, H, k, lv.A, Av, cur, r, l1, oth);
             std::swap(cur, oth);
         }
     }
@@ -600,7 +615,7 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready
     }
     csr<T>(h, 2, lv.P, P_<T>::v(lv.P), P_<T>::x(nx), nullptr, nullptr, cur);
     for (int it = 0; it < post; ++it) {
-        csr<T>(h, 3, lv.A, Av, cur, r, l1, oth);
+        sweep<T>(h, H, k, lv.A, Av, cur, r, l1, oth);
         std::swap(cur, oth);
     }
 }
@@ -1343,7 +1358,7 @@ int mgr_set_kernel_timing(mgr_handle *h, int on) {
 }
 
 int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launches, double *bytes_total) {
-    if (!h || kernel < 0 || kernel > 1) return MGR_E_INVALID;
+    if (!h || kernel < 0 || kernel > 2) return MGR_E_INVALID;
     try {
         sync(h);
         mgr_handle::Timer &t = h->tm[kernel];

@@ -109,7 +109,8 @@ struct mgr_handle {
     int *herr = nullptr;     // pinned host copy
 
     // event timing (mgr_set_kernel_timing): tm[0] the level-0 sliced-ELL kernel,
-    // tm[1] whole preconditioner applications (the V-cycle)
+    // tm[1] whole preconditioner applications (the V-cycle), tm[2] the l1-Jacobi
+    // sweeps on the coarse-grid matrix (level 0 of the coarse AMG hierarchy)
     struct Timer {
         std::vector<hipEvent_t> ev;
         size_t used = 0;
@@ -117,7 +118,7 @@ struct mgr_handle {
         int64_t launches = 0;
     };
     bool timing = false;
-    Timer tm[2];
+    Timer tm[3];
     double vc_bytes = 0;  // algorithmic bytes of the V-cycle being recorded
     double setup_ms = 0;
 };

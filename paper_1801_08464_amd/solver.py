@@ -174,7 +174,8 @@ class MGRSolver:
 
     def kernel_time(self, kernel=0):
         """(total ms, launches, algorithmic bytes) since timing was switched on or
-        last read; kernel 0 = level-0 sliced-ELL kernel, 1 = whole V-cycles."""
+        last read; kernel 0 = level-0 sliced-ELL kernel, 1 = whole V-cycles,
+        2 = the l1-Jacobi sweeps on the coarse-grid matrix."""
         ms, cnt, byt = C.c_double(), C.c_int64(), C.c_double()
         self._check(self.lib.mgr_kernel_time(self.h, int(kernel), C.byref(ms), C.byref(cnt), C.byref(byt)))
         return ms.value, cnt.value, byt.value

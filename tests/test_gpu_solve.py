@@ -202,8 +202,14 @@ def test_kernel_timing_counts_and_bytes():
     assert 12 * nnz + 4 * (n + 1) + 16 * n <= per0 <= 12 * nnz + 4 * (n + 1) + 24 * n
     # a V-cycle reads the level-0 matrix at least once
     assert b1 / n1 > 12 * nnz
+    # the coarse-grid sweeps: V(2,2) from zero is one sweep after the division, then two
+    ms2, n2, b2 = g.kernel_time(2)
+    assert n2 == 3 * info.iterations and ms2 > 0
+    A3 = g.get_matrix(3, 0)
+    n3, nnz3 = A3[3][0], len(A3[1])
+    assert b2 / n2 == 12 * nnz3 + 4 * (n3 + 1) + 8 * n3 + 3 * 8 * n3
     # counters reset after reading
     assert g.kernel_time(1)[1] == 0
     with pytest.raises(Exception):
-        g.kernel_time(2)
+        g.kernel_time(3)
     g.close()
