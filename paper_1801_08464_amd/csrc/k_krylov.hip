@@ -31,20 +31,31 @@ __device__ inline double block_sum(double v, double *sh) {
     return r;
 }
 
+// Basis-width template parameter: EXACT kernels are instantiated for nv == NV, so
+// their unrolled loops carry no per-vector branch and the loads of all basis
+// vectors are issued back to back (a branch per vector makes the compiler wait
+// for each load before the next).  The NV = 64 kernels serve wider bases with a
+// runtime guard.
+template <int NV, bool EXACT>
+__device__ inline bool has(int i, int nv) {
+    return EXACT || i < nv;
+}
+
 // Per-block partials of NV+1 running sums (entry NV holds <w, w>): wavefront
 // sums, then one synchronisation and a fixed-order sum over the 4 wavefronts.
-template <int NV>
+template <int NV, bool EXACT>
 __device__ inline void write_partials(const double (&acc)[NV + 1], int nv, double (*sh)[NV + 1], double *part) {
     const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
 #pragma unroll
     for (int i = 0; i <= NV; ++i) {
-        if (i < nv || i == NV) {  // uniform over the block
+        if (has<NV, EXACT>(i, nv) || i == NV) {  // uniform over the block
             const double v = wave_sum(acc[i]);
             if (l == 0) sh[wv][i] = v;
         }
     }
     __syncthreads();
     const int t = threadIdx.x;
+    if (EXACT) nv = NV;
     if (t <= nv) {
         const int i = t == nv ? NV : t;
         double s = sh[0][i];
@@ -59,7 +70,7 @@ __device__ inline const double2 *vec2(const double *base, int i, int64_t ld) {
 }
 
 // part[b*(nv+1) + i] = sum over this block's elements of w*V_i (i < nv), and w*w at i = nv
-template <int NV>
+template <int NV, bool EXACT>
 __global__ void __launch_bounds__(BT) k_mdot(int64_t n2, int64_t ld, int nv, const double *__restrict__ V,
                                              const double *__restrict__ w, double *__restrict__ part) {
     __shared__ double sh[BT / kWave][NV + 1];
@@ -72,7 +83,7 @@ __global__ void __launch_bounds__(BT) k_mdot(int64_t n2, int64_t ld, int nv, con
         const double2 wq = w2[q];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) {
+            if (has<NV, EXACT>(i, nv)) {
                 const double2 vq = vec2(V, i, ld)[q];
                 acc[i] = acc[i] + wq.x * vq.x;
                 acc[i] = acc[i] + wq.y * vq.y;
@@ -80,20 +91,20 @@ __global__ void __launch_bounds__(BT) k_mdot(int64_t n2, int64_t ld, int nv, con
         acc[NV] = acc[NV] + wq.x * wq.x;
         acc[NV] = acc[NV] + wq.y * wq.y;
     }
-    write_partials<NV>(acc, nv, sh, part);
+    write_partials<NV, EXACT>(acc, nv, sh, part);
 }
 
 // w -= sum_i h[i] V_i, then the partials of <w, V_i> and <w, w> for the updated w
 // (the projection of the first Gram-Schmidt pass fused with the dot products of
 // the second: V is read once for both)
-template <int NV>
+template <int NV, bool EXACT>
 __global__ void __launch_bounds__(BT) k_maxpy_dot(int64_t n2, int64_t ld, int nv, const double *__restrict__ V,
                                                   const double *__restrict__ h, double *__restrict__ w,
                                                   double *__restrict__ part) {
     __shared__ double sh[BT / kWave][NV + 1];
     double hh[NV], acc[NV + 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
+    for (int i = 0; i < NV; ++i) hh[i] = has<NV, EXACT>(i, nv) ? h[i] : 0.0;
 #pragma unroll
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
     double2 *w2 = reinterpret_cast<double2 *>(w);
@@ -103,7 +114,7 @@ __global__ void __launch_bounds__(BT) k_maxpy_dot(int64_t n2, int64_t ld, int nv
         double2 vq[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) {
+            if (has<NV, EXACT>(i, nv)) {
                 vq[i] = vec2(V, i, ld)[q];
                 wq.x = wq.x - hh[i] * vq[i].x;
                 wq.y = wq.y - hh[i] * vq[i].y;
@@ -111,18 +122,18 @@ __global__ void __launch_bounds__(BT) k_maxpy_dot(int64_t n2, int64_t ld, int nv
         w2[q] = wq;
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) {
+            if (has<NV, EXACT>(i, nv)) {
                 acc[i] = acc[i] + wq.x * vq[i].x;
                 acc[i] = acc[i] + wq.y * vq[i].y;
             }
         acc[NV] = acc[NV] + wq.x * wq.x;
         acc[NV] = acc[NV] + wq.y * wq.y;
     }
-    write_partials<NV>(acc, nv, sh, part);
+    write_partials<NV, EXACT>(acc, nv, sh, part);
 }
 
 // w -= sum_i h[i] V_i ; part[b] = partial of <w, w> after the update
-template <int NV>
+template <int NV, bool EXACT>
 __global__ void __launch_bounds__(BT) k_maxpy_norm(int64_t n2, int64_t ld, int nv, const double *__restrict__ V,
                                                    const double *__restrict__ h, double *__restrict__ w,
                                                    double *__restrict__ part, const int *guard) {
@@ -130,7 +141,7 @@ __global__ void __launch_bounds__(BT) k_maxpy_norm(int64_t n2, int64_t ld, int n
     __shared__ double sh[BT / kWave];
     double hh[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) hh[i] = i < nv ? h[i] : 0.0;
+    for (int i = 0; i < NV; ++i) hh[i] = has<NV, EXACT>(i, nv) ? h[i] : 0.0;
     double acc = 0.0;
     double2 *w2 = reinterpret_cast<double2 *>(w);
     const int64_t stride = (int64_t)gridDim.x * BT;
@@ -138,7 +149,7 @@ __global__ void __launch_bounds__(BT) k_maxpy_norm(int64_t n2, int64_t ld, int n
         double2 wq = w2[q];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) {
+            if (has<NV, EXACT>(i, nv)) {
                 const double2 vq = vec2(V, i, ld)[q];
                 wq.x = wq.x - hh[i] * vq.x;
                 wq.y = wq.y - hh[i] * vq.y;
@@ -151,18 +162,18 @@ __global__ void __launch_bounds__(BT) k_maxpy_norm(int64_t n2, int64_t ld, int n
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-template <int NV>
+template <int NV, bool EXACT>
 __global__ void __launch_bounds__(BT) k_zaxpy(int64_t n, int64_t ld, int nv, const double *__restrict__ Z,
                                               const double *__restrict__ y, double *__restrict__ x) {
     double yy[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) yy[i] = i < nv ? y[i] : 0.0;
+    for (int i = 0; i < NV; ++i) yy[i] = has<NV, EXACT>(i, nv) ? y[i] : 0.0;
     const int64_t stride = (int64_t)gridDim.x * BT;
     for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < n; q += stride) {
         double s = x[q];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
-            if (i < nv) s = s + yy[i] * Z[(int64_t)i * ld + q];
+            if (has<NV, EXACT>(i, nv)) s = s + yy[i] * Z[(int64_t)i * ld + q];
         x[q] = s;
     }
 }
@@ -288,14 +299,33 @@ static unsigned red_grid(int64_t n) {
 
 int64_t krylov_ld(int64_t n) { return (n + 63) / 64 * 64; }
 
-#define MGR_NV_DISPATCH(KERNEL, nv, ...)                                          \
-    do {                                                                          \
-        if ((nv) <= 4) KERNEL<4><<<g, BT, 0, s>>>(__VA_ARGS__);                   \
-        else if ((nv) <= 8) KERNEL<8><<<g, BT, 0, s>>>(__VA_ARGS__);              \
-        else if ((nv) <= 16) KERNEL<16><<<g, BT, 0, s>>>(__VA_ARGS__);            \
-        else if ((nv) <= 32) KERNEL<32><<<g, BT, 0, s>>>(__VA_ARGS__);            \
-        else KERNEL<kMaxV><<<g, BT, 0, s>>>(__VA_ARGS__);                         \
+// nv <= kFusedMaxV: the kernel instantiated for exactly nv vectors; wider
+// bases: the guarded kMaxV kernel
+#define MGR_NV_CASE(KERNEL, N, ...) \
+    case N: KERNEL<N, true><<<g, BT, 0, s>>>(__VA_ARGS__); break;
+#define MGR_NV_DISPATCH(KERNEL, nv, ...)                                                                 \
+    do {                                                                                                 \
+        switch (nv) {                                                                                    \
+            MGR_NV_CASE(KERNEL, 1, __VA_ARGS__) MGR_NV_CASE(KERNEL, 2, __VA_ARGS__)                      \
+            MGR_NV_CASE(KERNEL, 3, __VA_ARGS__) MGR_NV_CASE(KERNEL, 4, __VA_ARGS__)                      \
+            MGR_NV_CASE(KERNEL, 5, __VA_ARGS__) MGR_NV_CASE(KERNEL, 6, __VA_ARGS__)                      \
+            MGR_NV_CASE(KERNEL, 7, __VA_ARGS__) MGR_NV_CASE(KERNEL, 8, __VA_ARGS__)                      \
+            MGR_NV_CASE(KERNEL, 9, __VA_ARGS__) MGR_NV_CASE(KERNEL, 10, __VA_ARGS__)                     \
+            MGR_NV_CASE(KERNEL, 11, __VA_ARGS__) MGR_NV_CASE(KERNEL, 12, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 13, __VA_ARGS__) MGR_NV_CASE(KERNEL, 14, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 15, __VA_ARGS__) MGR_NV_CASE(KERNEL, 16, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 17, __VA_ARGS__) MGR_NV_CASE(KERNEL, 18, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 19, __VA_ARGS__) MGR_NV_CASE(KERNEL, 20, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 21, __VA_ARGS__) MGR_NV_CASE(KERNEL, 22, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 23, __VA_ARGS__) MGR_NV_CASE(KERNEL, 24, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 25, __VA_ARGS__) MGR_NV_CASE(KERNEL, 26, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 27, __VA_ARGS__) MGR_NV_CASE(KERNEL, 28, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 29, __VA_ARGS__) MGR_NV_CASE(KERNEL, 30, __VA_ARGS__)                    \
+            MGR_NV_CASE(KERNEL, 31, __VA_ARGS__) MGR_NV_CASE(KERNEL, 32, __VA_ARGS__)                    \
+        default: KERNEL<kMaxV, false><<<g, BT, 0, s>>>(__VA_ARGS__); break;                              \
+        }                                                                                                \
     } while (0)
+static_assert(kFusedMaxV == 32, "the exact-width dispatch covers 1..32 vectors");
 
 void launch_mdot(int64_t n, int64_t ld, int nv, const double *V, const double *w, double *part, hipStream_t s) {
     const int64_t n2 = (n + 1) / 2;
@@ -307,14 +337,12 @@ void launch_maxpy_dot(int64_t n, int64_t ld, int nv, const double *V, const doub
                       hipStream_t s) {
     const int64_t n2 = (n + 1) / 2;
     const unsigned g = red_grid(n);
-    if (nv <= 4) k_maxpy_dot<4><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
-    else if (nv <= 8) k_maxpy_dot<8><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
-    else if (nv <= 16) k_maxpy_dot<16><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
-    else if (nv <= kFusedMaxV) k_maxpy_dot<kFusedMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part);
-    else {
+    if (nv <= kFusedMaxV) {
+        MGR_NV_DISPATCH(k_maxpy_dot, nv, n2, ld, nv, V, h, w, part);
+    } else {
         // too wide to hold the basis values in registers: update, then dot
-        k_maxpy_norm<kMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part, nullptr);
-        k_mdot<kMaxV><<<g, BT, 0, s>>>(n2, ld, nv, V, w, part);
+        k_maxpy_norm<kMaxV, false><<<g, BT, 0, s>>>(n2, ld, nv, V, h, w, part, nullptr);
+        k_mdot<kMaxV, false><<<g, BT, 0, s>>>(n2, ld, nv, V, w, part);
     }
 }
 
@@ -331,6 +359,7 @@ void launch_zaxpy(int64_t n, int64_t ld, int nv, const double *Z, const double *
     MGR_NV_DISPATCH(k_zaxpy, nv, n, ld, nv, Z, y, x);
 }
 #undef MGR_NV_DISPATCH
+#undef MGR_NV_CASE
 
 void launch_norm_part(int64_t n, const double *a, double *part, hipStream_t s) {
     k_norm_part<<<red_grid(n), BT, 0, s>>>(n, a, part);

@@ -12,7 +12,7 @@ namespace {
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
 // CSR "stream" SpMV: a workgroup owns ROWS consecutive rows.  Their nonzeros are
-// read as one contiguous, coalesced stream in passes of kStreamLds entries; in a
+// read as one contiguous, coalesced stream in passes of LDSN entries; in a
 // pass each thread issues the column and value loads of all its entries before
 // their dependent gathers of x, and stages the products v*x in LDS (the loads of
 // pass p+1 are issued before the row sums of pass p, so they overlap).  Then thread t
@@ -23,7 +23,9 @@ __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + thr
 // Modes: 0 y = Ax; 1 y = r - Ax; 2 y += Ax; 3 y = x + (r - Ax)/d (Jacobi sweep);
 // 4 y = Ax and y2 = y/d (a restriction that also forms the next level's first
 // Jacobi iterate from zero, the division the separate pass would do).
-constexpr int kStreamLds = 4096;
+// LDSN (entries per pass) follows the matrix's mean row length: short-row
+// operators (P, R, the F-blocks) fill a 4096-entry pass only partly, and a
+// smaller pass lets more workgroups share a CU.
 
 template <typename T, int MODE>
 __device__ inline void row_store(int64_t row, T acc, const T *__restrict__ x, const T *__restrict__ r,
@@ -38,13 +40,12 @@ __device__ inline void row_store(int64_t row, T acc, const T *__restrict__ x, co
     }
 }
 
-template <typename T, int MODE, int ROWS>
+template <typename T, int MODE, int ROWS, int LDSN>
 __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ ci, const T *__restrict__ v,
                                                      const T *__restrict__ x, const T *__restrict__ r,
                                                      const T *__restrict__ d, T *__restrict__ y,
                                                      T *__restrict__ y2) {
-    constexpr int LDSN = kStreamLds;
     constexpr int B = LDSN / ROWS;  // entries per thread per pass
     __shared__ T sh[LDSN];
     const int tid = threadIdx.x;
@@ -262,11 +263,11 @@ __global__ void __launch_bounds__(kWave) k_lu_solve_wave(int n, const double *__
 
 constexpr int BT = 256;
 
-template <typename T, int ROWS>
+template <typename T, int ROWS, int LDSN>
 static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
                      hipStream_t s) {
     const unsigned g = nblocks(A.nrows, ROWS);
-#define MGR_STREAM(M) k_csr_stream<T, M, ROWS><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2)
+#define MGR_STREAM(M) k_csr_stream<T, M, ROWS, LDSN><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2)
     switch (mode) {
     case 0: MGR_STREAM(0); break;
     case 1: MGR_STREAM(1); break;
@@ -296,6 +297,9 @@ static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const
 // hierarchy: stream everywhere costs 40 % more solve time, lanes on levels of up
 // to 600k rows about 1 % more)
 constexpr int64_t kCsrStreamMinRows = 131072;
+// mean row lengths below which the stream kernel takes 1024- and 2048-entry passes
+constexpr double kStreamShortRow = 3.0;
+constexpr double kStreamMidRow = 8.0;
 
 // Large levels: 256-row stream workgroups (sequential row sums).  Small levels,
 // where those would leave most CUs idle: several lanes per row.
@@ -303,11 +307,13 @@ template <typename T>
 static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
                     hipStream_t s) {
     if (A.nrows <= 0) return;
+    const double avg = (double)A.nnz / (double)A.nrows;
     if (A.nrows >= kCsrStreamMinRows) {
-        csr_rows<T, 256>(mode, A, vals, x, r, d, y, y2, s);
+        if (avg < kStreamShortRow) csr_rows<T, 256, 1024>(mode, A, vals, x, r, d, y, y2, s);
+        else if (avg < kStreamMidRow) csr_rows<T, 256, 2048>(mode, A, vals, x, r, d, y, y2, s);
+        else csr_rows<T, 256, 4096>(mode, A, vals, x, r, d, y, y2, s);
         return;
     }
-    const double avg = (double)A.nnz / (double)A.nrows;
     const int lanes = avg < 3 ? 2 : avg < 6 ? 4 : avg < 12 ? 8 : avg < 24 ? 16 : 32;
     switch (mode) {
     case 0: csr_lanes<T, 0>(A, lanes, vals, x, r, d, y, y2, s); break;
