@@ -27,18 +27,32 @@ __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + thr
 // operators (P, R, the F-blocks) fill a 4096-entry pass only partly, and a
 // smaller pass lets more workgroups share a CU.
 
+// The per-row operands of the output step (the lanes kernel loads them before
+// the row's sum so that their latency overlaps it).
 template <typename T, int MODE>
-__device__ inline void row_store(int64_t row, T acc, const T *__restrict__ x, const T *__restrict__ r,
-                                 const T *__restrict__ d, T *__restrict__ y, T *__restrict__ y2) {
-    if (MODE == 0) y[row] = acc;
-    else if (MODE == 1) y[row] = r[row] - acc;
-    else if (MODE == 2) y[row] = y[row] + acc;
-    else if (MODE == 3) y[row] = x[row] + (r[row] - acc) / d[row];
-    else {
-        y[row] = acc;
-        y2[row] = acc / d[row];
+struct RowIn {
+    T a = 0, b = 0, c = 0;
+    __device__ inline void load(int64_t row, const T *__restrict__ x, const T *__restrict__ r,
+                                const T *__restrict__ d, const T *__restrict__ y) {
+        if (MODE == 1) a = r[row];
+        if (MODE == 2) a = y[row];
+        if (MODE == 3) {
+            a = x[row];
+            b = r[row];
+        }
+        if (MODE == 3 || MODE == 4) c = d[row];
     }
-}
+    __device__ inline void store(int64_t row, T acc, T *__restrict__ y, T *__restrict__ y2) const {
+        if (MODE == 0) y[row] = acc;
+        else if (MODE == 1) y[row] = a - acc;
+        else if (MODE == 2) y[row] = a + acc;
+        else if (MODE == 3) y[row] = a + (b - acc) / c;
+        else {
+            y[row] = acc;
+            y2[row] = acc / c;
+        }
+    }
+};
 
 template <typename T, int MODE, int ROWS, int LDSN>
 __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
@@ -88,7 +102,11 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
         for (int p = lo; p < hi; ++p) acc = acc + sh[p - base];
         __syncthreads();
     }
-    if (row < re) row_store<T, MODE>(row, acc, x, r, d, y, y2);
+    if (row < re) {
+        RowIn<T, MODE> in;
+        in.load(row, x, r, d, y);
+        in.store(row, acc, y, y2);
+    }
 }
 
 // Row-list kernels on the compact copy of a level's F rows (row f of AF is row
@@ -147,11 +165,26 @@ __global__ void __launch_bounds__(256) k_csr_lanes(int64_t nrows, const int32_t 
     const int64_t row = gid / LANES;
     const int sub = (int)(gid % LANES);
     T s = 0;
-    if (row < nrows)
-        for (int p = rp[row] + sub; p < rp[row + 1]; p += LANES) s = s + v[p] * x[ci[p]];
+    RowIn<T, MODE> in;
+    if (row < nrows && sub == 0) in.load(row, x, r, d, y);
+    if (row < nrows) {
+        // two strides per trip, both gathers issued before either product is
+        // added (the additions keep the stride order)
+        const int pe = rp[row + 1];
+        for (int p = rp[row] + sub; p < pe; p += 2 * LANES) {
+            const int q = p + LANES;
+            const int c0 = ci[p];
+            const T v0 = v[p];
+            const int c1 = q < pe ? ci[q] : c0;
+            const T v1 = q < pe ? v[q] : (T)0;
+            const T x0 = x[c0], x1 = x[c1];
+            s = s + v0 * x0;
+            if (q < pe) s = s + v1 * x1;
+        }
+    }
 #pragma unroll
     for (int o = LANES / 2; o > 0; o >>= 1) s = s + __shfl_xor(s, o);
-    if (row < nrows && sub == 0) row_store<T, MODE>(row, s, x, r, d, y, y2);
+    if (row < nrows && sub == 0) in.store(row, s, y, y2);
 }
 
 // e = B^{-1} r per cell (ADD: e += B^{-1} r)
