@@ -34,6 +34,30 @@ def test_vcycle_matches_oracle(orc, precision, post):
     g.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_vcycle_with_stream_amg_levels_matches_oracle(orc, precision):
+    # 52^3 cells: the coarse-grid matrix has 140,608 rows of ~23 entries, so its
+    # sweeps and residuals run in the 256-row stream kernel with 4096-entry passes
+    # (the V-cycle tests above only reach the small-level kernels)
+    s = small_system((52, 52, 52), seed=6, sigma=2.0, frac=0.3, region="ball")
+    print(f"[vcycle stream levels] n={s.n} {precision}", flush=True)
+    o = orc.Oracle(oracle_csr(orc, s), s.labels, precision=1 if precision == "mixed" else 0, frelax_amg_mask=2)
+    g = gpu_solver(s, precision=precision, frelax_amg_mask=2)
+    rp3 = g.get_matrix(3, 0)[0]
+    n3 = rp3.shape[0] - 1
+    assert n3 >= 131072 and rp3[-1] >= 12 * n3
+    r = random_vector(s.n, 2)
+    z = g.apply_preconditioner(r).cpu().numpy()
+    ze = o.vcycle(r)
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    assert np.linalg.norm(z - ze) / np.linalg.norm(ze) < tol
+    # the same input twice gives the same bits
+    z2 = g.apply_preconditioner(r).cpu().numpy()
+    np.testing.assert_array_equal(z, z2)
+    o.close()
+    g.close()
+
+
 @pytest.mark.parametrize("cfg", [1, "3d"])
 def test_solve_matches_oracle(orc, cfg):
     s = make_config(1) if cfg == 1 else small_system((24, 24, 24), seed=3, sigma=1.5, frac=0.35, region="ball")
