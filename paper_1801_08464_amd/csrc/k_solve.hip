@@ -236,6 +236,29 @@ __global__ void k_gather(int64_t n, const int32_t *__restrict__ idx, const T *__
     if (i < n) dst[i] = src[idx[i]];
 }
 
+// t[f] = r[idx[f]] and x0[f] = t[f] / d[f] (the gathered right-hand side and the
+// first Jacobi iterate from zero of the hierarchy it feeds)
+template <typename T>
+__global__ void k_gather_div(int64_t n, const int32_t *__restrict__ idx, const T *__restrict__ src,
+                             const T *__restrict__ d, T *__restrict__ dst, T *__restrict__ x0) {
+    const int64_t i = gtid();
+    if (i >= n) return;
+    const T v = src[idx[i]];
+    dst[i] = v;
+    x0[i] = v / d[i];
+}
+
+// e[i] = 0 + d[map[i]] where map[i] >= 0, else 0 (the zero fill and the scatter
+// of the F-point correction in one pass)
+template <typename T>
+__global__ void k_scatter_set(int64_t n, const int32_t *__restrict__ map, const T *__restrict__ d,
+                              T *__restrict__ e) {
+    const int64_t i = gtid();
+    if (i >= n) return;
+    const int f = map[i];
+    e[i] = f >= 0 ? (T)0 + d[f] : (T)0;
+}
+
 template <typename T>
 __global__ void k_scatter_add(int64_t n, const int32_t *__restrict__ idx, const T *__restrict__ d, T *__restrict__ e) {
     const int64_t i = gtid();
@@ -438,6 +461,16 @@ void launch_scatter_add(int64_t n, const int32_t *idx, const T *d, T *e, hipStre
 }
 
 template <typename T>
+void launch_gather_div(int64_t n, const int32_t *idx, const T *src, const T *d, T *dst, T *x0, hipStream_t s) {
+    if (n > 0) k_gather_div<T><<<nblocks(n, BT), BT, 0, s>>>(n, idx, src, d, dst, x0);
+}
+
+template <typename T>
+void launch_scatter_set(int64_t n, const int32_t *map, const T *d, T *e, hipStream_t s) {
+    if (n > 0) k_scatter_set<T><<<nblocks(n, BT), BT, 0, s>>>(n, map, d, e);
+}
+
+template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s) {
     if (n <= 0) return;
     if (n <= kWave) k_lu_solve_wave<T><<<1, kWave, 0, s>>>((int)n, lu, perm, b, x);
@@ -457,6 +490,8 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
     template void launch_div<T>(int64_t, const T *, const T *, T *, hipStream_t);                               \
     template void launch_gather<T>(int64_t, const int32_t *, const T *, T *, hipStream_t);                      \
     template void launch_scatter_add<T>(int64_t, const int32_t *, const T *, T *, hipStream_t);                 \
+    template void launch_gather_div<T>(int64_t, const int32_t *, const T *, const T *, T *, T *, hipStream_t);   \
+    template void launch_scatter_set<T>(int64_t, const int32_t *, const T *, T *, hipStream_t);                 \
     template void launch_lu_solve<T>(int64_t, const double *, const int32_t *, const T *, T *, hipStream_t);
 
 MGR_INSTANTIATE(double)

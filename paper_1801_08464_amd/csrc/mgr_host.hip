@@ -565,6 +565,22 @@ void sweep(mgr_handle *h, const AmgHier &H, int k, const DCsr &A, const T *vals,
     }
 }
 
+// Where level k of H (not its coarsest) reads its first Jacobi iterate when the
+// cycle's output goes to x: the sweeps ping-pong between x and x2, arranged so
+// that the last one writes x.
+template <typename T>
+T *amg_x0_buffer(AmgHier &H, int k, T *x) {
+    const int swaps = (H.pre > 0 ? H.pre - 1 : 0) + H.post;
+    return (swaps % 2 == 0) ? x : P_<T>::x2(H.lev[k]);
+}
+
+// the first sweep of level 0 of H can start from an x0 = r / l1 written by the
+// caller's restriction or gather
+template <typename T>
+bool amg_takes_x0(const AmgHier &H) {
+    return H.pre > 0 && H.lev.size() > 1;
+}
+
 // x0_ready: the caller's restriction already wrote x0 = r / l1 (the first Jacobi
 // iterate from zero) where this level's first sweep reads it
 template <typename T>
@@ -582,8 +598,7 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready
     const T *l1 = P_<T>::l1(lv);
     const int pre = H.pre, post = H.post;
     // ping-pong buffers arranged so that the last sweep writes x
-    const int swaps = (pre > 0 ? pre - 1 : 0) + post;
-    T *cur = (swaps % 2 == 0) ? x : P_<T>::x2(lv);
+    T *cur = amg_x0_buffer<T>(H, k, x);
     T *oth = (cur == x) ? P_<T>::x2(lv) : x;
     for (int it = 0; it < pre; ++it) {
         if (it == 0) {
@@ -605,7 +620,7 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready
     AmgLevel &nx = H.lev[k + 1];
     if (pre > 0 && k + 1 < (int)H.lev.size() - 1) {
         // restriction + the next level's x0 = r / l1, written where its first sweep reads it
-        T *nx_cur = (swaps % 2 == 0) ? P_<T>::x(nx) : P_<T>::x2(nx);
+        T *nx_cur = amg_x0_buffer<T>(H, k + 1, P_<T>::x(nx));
         launch_csr_restrict_div<T>(lv.PT, P_<T>::v(lv.PT), t, P_<T>::l1(nx), P_<T>::r(nx), nx_cur, s);
         acct(h, csr_bytes(lv.PT, 0, S) + 2.0 * S * (double)nx.n);
         amg_cycle<T>(h, H, k + 1, P_<T>::r(nx), P_<T>::x(nx), true);
@@ -620,10 +635,12 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready
     }
 }
 
+// x0_ready (l == L only): the restriction into the coarse grid already wrote the
+// first Jacobi iterate of the coarse-grid AMG cycle
 template <typename T>
-void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
+void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
     if (l == h->L) {
-        amg_cycle<T>(h, h->cg, 0, r, e);
+        amg_cycle<T>(h, h->cg, 0, r, e, x0_ready);
         return;
     }
     MgrLevel &lv = h->lev[l];
@@ -642,6 +659,20 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
         rc = P_<T>::r(h->cg.lev[0]);
         ec = P_<T>::x(h->cg.lev[0]);
     }
+    // restriction rc = R src, then the next level's cycle; into the coarse grid the
+    // restriction also writes the AMG cycle's first Jacobi iterate rc / l1
+    auto coarse_correction = [&](const T *src) {
+        if (l + 1 == h->L && amg_takes_x0<T>(h->cg)) {
+            AmgLevel &c0 = h->cg.lev[0];
+            launch_csr_restrict_div<T>(lv.R, P_<T>::v(lv.R), src, P_<T>::l1(c0), rc, amg_x0_buffer<T>(h->cg, 0, ec),
+                                       s);
+            acct(h, csr_bytes(lv.R, 0, S) + 2.0 * S * (double)c0.n);
+            mgr_cycle<T>(h, l + 1, rc, ec, true);
+        } else {
+            csr<T>(h, 0, lv.R, P_<T>::v(lv.R), src, nullptr, nullptr, rc);
+            mgr_cycle<T>(h, l + 1, rc, ec);
+        }
+    };
     // F-relaxation sweeps: Jacobi with diag(A_FF), or one AMG V-cycle on A_FF;
     // `have` tells whether e already holds a value (else e = 0 is implied)
     auto frelax = [&](bool have) {
@@ -650,17 +681,28 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
                 AmgLevel &f0 = lv.ff->lev[0];
                 T *rF = P_<T>::r(f0), *dF = P_<T>::x(f0);
                 if (!have) {
-                    launch_gather<T>(lv.nF, lv.flist, r, rF, s);
-                    P_<T>::fill(e, lv.n, s);
-                    acct(h, 4.0 * nF + 2.0 * S * nF + S * n);
+                    // from e = 0: gather r_F (with the AMG cycle's first iterate
+                    // r_F / l1 where the cycle takes it), cycle, then e = 0 + d on F
+                    // and 0 on C in one pass
+                    if (amg_takes_x0<T>(*lv.ff)) {
+                        launch_gather_div<T>(lv.nF, lv.flist, r, P_<T>::l1(f0), rF, amg_x0_buffer<T>(*lv.ff, 0, dF), s);
+                        acct(h, 4.0 * nF + 4.0 * S * nF);
+                        amg_cycle<T>(h, *lv.ff, 0, rF, dF, true);
+                    } else {
+                        launch_gather<T>(lv.nF, lv.flist, r, rF, s);
+                        acct(h, 4.0 * nF + 2.0 * S * nF);
+                        amg_cycle<T>(h, *lv.ff, 0, rF, dF);
+                    }
+                    launch_scatter_set<T>(lv.n, lv.fmap, dF, e, s);
+                    acct(h, 4.0 * n + S * nF + S * n);
                     have = true;
                 } else {
                     launch_csr_rows_residual<T>(lv.AF, lv.flanes, P_<T>::v(lv.AF), lv.nF, lv.flist, e, r, rF, s);
                     acct(h, afb + 2.0 * S * nF);
+                    amg_cycle<T>(h, *lv.ff, 0, rF, dF);
+                    launch_scatter_add<T>(lv.nF, lv.flist, dF, e, s);
+                    acct(h, 4.0 * nF + 3.0 * S * nF);
                 }
-                amg_cycle<T>(h, *lv.ff, 0, rF, dF);
-                launch_scatter_add<T>(lv.nF, lv.flist, dF, e, s);
-                acct(h, 4.0 * nF + 3.0 * S * nF);
             } else if (!have) {
                 launch_frelax_first<T>(lv.n, lv.fmap, dinv, r, e, s);
                 acct(h, 4.0 * n + S * nF + 2.0 * S * n);
@@ -681,8 +723,7 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
     if (h->o.cycle_post) {
         // eq. MGR-post: coarse-grid correction from e = 0, then the smoother in the
         // reverse order of the pre-smoothing steps (F-relaxation, global relaxation)
-        csr<T>(h, 0, lv.R, P_<T>::v(lv.R), r, nullptr, nullptr, rc);
-        mgr_cycle<T>(h, l + 1, rc, ec);
+        coarse_correction(r);
         csr<T>(h, 0, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
         frelax(true);
         if (global) {
@@ -708,8 +749,7 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e) {
     // (3) coarse-grid correction e += P M_c^{-1} R (r - A e)
     if (l == 0) fine_op<T>(h, 1, e, r, t);
     else csr<T>(h, 1, lv.A, Av, e, r, nullptr, t);
-    csr<T>(h, 0, lv.R, P_<T>::v(lv.R), t, nullptr, nullptr, rc);
-    mgr_cycle<T>(h, l + 1, rc, ec);
+    coarse_correction(t);
     csr<T>(h, 2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
 }
 

@@ -243,6 +243,12 @@ template <typename T>
 void launch_gather(int64_t n, const int32_t *idx, const T *src, T *dst, hipStream_t s);
 template <typename T>
 void launch_scatter_add(int64_t n, const int32_t *idx, const T *d, T *e, hipStream_t s);
+// t[f] = r[idx[f]] and x0[f] = t[f] / d[f]
+template <typename T>
+void launch_gather_div(int64_t n, const int32_t *idx, const T *src, const T *d, T *dst, T *x0, hipStream_t s);
+// e[i] = 0 + d[map[i]] where map[i] >= 0, else 0
+template <typename T>
+void launch_scatter_set(int64_t n, const int32_t *map, const T *d, T *e, hipStream_t s);
 template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s);
 
