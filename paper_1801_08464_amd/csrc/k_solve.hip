@@ -11,6 +11,18 @@ namespace {
 
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
+// Workgroups are dealt to the 8 XCDs round-robin.  Renumber them so that each
+// XCD takes kXcdGroup consecutive row blocks before moving on (64 blocks of 256
+// rows: one 128 x 128 grid plane, whose neighbours' x values then stay in that
+// XCD's L2); a tail shorter than 8 groups keeps the plain order.
+constexpr int64_t kXcdGroup = 64;
+__device__ inline int64_t xcd_grouped_block() {
+    const int64_t b = blockIdx.x, span = 8 * kXcdGroup;
+    if (b >= (int64_t)gridDim.x / span * span) return b;
+    const int64_t xcd = b % 8, i = b / 8;
+    return ((i / kXcdGroup) * 8 + xcd) * kXcdGroup + i % kXcdGroup;
+}
+
 // CSR "stream" SpMV: a workgroup owns ROWS consecutive rows.  Their nonzeros are
 // read as one contiguous, coalesced stream in passes of LDSN entries; in a
 // pass each thread issues the column and value loads of all its entries before
@@ -63,7 +75,7 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
     constexpr int B = LDSN / ROWS;  // entries per thread per pass
     __shared__ T sh[LDSN];
     const int tid = threadIdx.x;
-    const int64_t rb = (int64_t)blockIdx.x * ROWS;
+    const int64_t rb = xcd_grouped_block() * ROWS;
     const int64_t re = rb + ROWS < nrows ? rb + ROWS : nrows;
     const int64_t row = rb + tid;
     const int p0 = rp[rb], p1 = rp[re];
