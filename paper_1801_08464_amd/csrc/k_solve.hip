@@ -26,8 +26,9 @@ __device__ inline int64_t xcd_grouped_block() {
 // CSR "stream" SpMV: a workgroup owns ROWS consecutive rows.  Their nonzeros are
 // read as one contiguous, coalesced stream in passes of LDSN entries; in a
 // pass each thread issues the column and value loads of all its entries before
-// their dependent gathers of x, and stages the products v*x in LDS (the loads of
-// pass p+1 are issued before the row sums of pass p, so they overlap).  Then thread t
+// their dependent gathers of x, and stages the products v*x in LDS (other
+// workgroups on the CU overlap a pass's loads with its row sums; issuing the
+// next pass's loads early costs more in registers than it saves).  Then thread t
 // sums row rb+t sequentially in ascending column order (a row's entries may span
 // several passes, which run in ascending order).  No padding, any row-length mix,
 // and the same summation order per row as a sequential CSR loop.  The matrix is
@@ -87,7 +88,6 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
     T acc = 0;
     int j[B];
     T av[B];
-    // the column/value loads of pass p+1 are issued before pass p's row sums
     auto load_pass = [&](int base) {
         const int lim = base + LDSN < p1 ? base + LDSN : p1;
 #pragma unroll
@@ -97,9 +97,9 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
             av[u] = p < lim ? __builtin_nontemporal_load(v + p) : (T)0;
         }
     };
-    if (p0 < p1) load_pass(p0);
     for (int base = p0; base < p1; base += LDSN) {
         const int lim = base + LDSN < p1 ? base + LDSN : p1;
+        load_pass(base);
         T xv[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
@@ -109,7 +109,6 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
             if (p < lim) sh[p - base] = av[u] * xv[u];
         }
         __syncthreads();
-        if (base + LDSN < p1) load_pass(base + LDSN);
         const int lo = a > base ? a : base, hi = b < lim ? b : lim;
         for (int p = lo; p < hi; ++p) acc = acc + sh[p - base];
         __syncthreads();
