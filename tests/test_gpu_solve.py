@@ -193,6 +193,15 @@ def test_status_codes_through_the_abi():
     g.close()
 
 
+def test_empty_system_is_rejected():
+    # n = 0: the setup refuses it (no partial handle is returned)
+    from paper_1801_08464_amd import binding as B
+    from paper_1801_08464_amd.solver import MGRSolver
+    with pytest.raises(B.MGRError) as e:
+        MGRSolver(np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0, np.int32))
+    assert e.value.code == B.E_INVALID
+
+
 def test_amg_frelaxation_solve_matched_iterations(orc):
     s = small_system((20, 20, 20), seed=4, sigma=2.0, frac=0.3, region="ball")
     A = oracle_csr(orc, s)
