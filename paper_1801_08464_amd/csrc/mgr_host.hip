@@ -35,6 +35,28 @@ struct Fail {
     throw Fail{code};
 }
 
+// Inside a catch handler of a C-ABI entry point: the status code of the
+// exception in flight (no exception may cross the C boundary).
+int abi_status(mgr_handle *h) {
+    try {
+        throw;
+    } catch (const Fail &f) {
+        return f.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        if (h) h->err = g_err;
+        return MGR_E_OOM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        if (h) h->err = g_err;
+        return MGR_E_INVALID;
+    } catch (...) {
+        g_err = "unexpected error";
+        if (h) h->err = g_err;
+        return MGR_E_INVALID;
+    }
+}
+
 void sync(mgr_handle *h) { HIPCHK(hipStreamSynchronize(h->stream)); }
 
 template <typename T>
@@ -1053,13 +1075,10 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
         h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         *out = h;
         return MGR_OK;
-    } catch (const Fail &f) {
+    } catch (...) {
+        const int rc = abi_status(nullptr);
         destroy_impl(h);
-        return f.code;
-    } catch (const std::bad_alloc &) {
-        destroy_impl(h);
-        g_err = "host allocation failed";
-        return MGR_E_OOM;
+        return rc;
     }
 }
 
@@ -1104,9 +1123,9 @@ int alloc(mgr_handle *h, void **p, size_t bytes) {
     try {
         *p = arena_alloc(h, h->keep, bytes);
         return MGR_OK;
-    } catch (const Fail &f) {
+    } catch (...) {
         *p = nullptr;
-        return f.code;
+        return abi_status(h);
     }
 }
 }  // namespace mgr
@@ -1161,8 +1180,8 @@ int mgr_solve(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *
         }
         if (rc == MGR_E_BREAKDOWN) h->err = "NaN or Inf in the right-hand side or the Krylov recurrence";
         return rc;
-    } catch (const Fail &f) {
-        return f.code;
+    } catch (...) {
+        return abi_status(h);
     }
 }
 
@@ -1172,8 +1191,8 @@ int mgr_pattern_outer(mgr_handle *h, const double *lambda, const double *x, doub
         launch_pattern_outer(h->Ain.nrows, h->Ain.rp, h->Ain.ci, lambda, x, dvals, h->stream);
         HIPCHK(hipGetLastError());
         return MGR_OK;
-    } catch (const Fail &f) {
-        return f.code;
+    } catch (...) {
+        return abi_status(h);
     }
 }
 
@@ -1183,8 +1202,8 @@ int mgr_apply_preconditioner(mgr_handle *h, const double *r, double *z) {
         apply_prec(h, r, z);
         sync(h);
         return MGR_OK;
-    } catch (const Fail &f) {
-        return f.code;
+    } catch (...) {
+        return abi_status(h);
     }
 }
 
@@ -1194,8 +1213,8 @@ int mgr_spmv(mgr_handle *h, const double *x, double *y) {
         fine_op<double>(h, 0, x, nullptr, y);
         sync(h);
         return MGR_OK;
-    } catch (const Fail &f) {
-        return f.code;
+    } catch (...) {
+        return abi_status(h);
     }
 }
 
@@ -1265,8 +1284,8 @@ int mgr_get_matrix(mgr_handle *h, int kind, int level, int64_t *nrows, int64_t *
         if (col_idx && M->nnz) HIPCHK(hipMemcpy(col_idx, M->ci, M->nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
         if (values && M->v && M->nnz) HIPCHK(hipMemcpy(values, M->v, M->nnz * sizeof(double), hipMemcpyDeviceToHost));
         return MGR_OK;
-    } catch (const Fail &f) {
-        return f.code;
+    } catch (...) {
+        return abi_status(h);
     }
 }
 
@@ -1312,8 +1331,8 @@ int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len) 
             HIPCHK(hipMemcpy(out, src, n * esz, hipMemcpyDeviceToHost));
         }
         return MGR_OK;
-    } catch (const Fail &f) {
-        return f.code;
+    } catch (...) {
+        return abi_status(h);
     }
 }
 
@@ -1353,8 +1372,8 @@ int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double 
         if (rnorm) *rnorm = rn;
         if (nactive) *nactive = na;
         return std::isfinite(rn) ? MGR_OK : MGR_E_BREAKDOWN;
-    } catch (const Fail &e) {
-        return e.code;
+    } catch (...) {
+        return abi_status(nullptr);
     }
 }
 
@@ -1381,8 +1400,8 @@ int mgr_ncp_jacobian(const mgr_csr *L, const double *henry, const int32_t *label
                             h->stream);
         sync(h);
         return MGR_OK;
-    } catch (const Fail &e) {
-        return e.code;
+    } catch (...) {
+        return abi_status(nullptr);
     }
 }
 
@@ -1415,8 +1434,8 @@ int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launch
         t.bytes = 0;
         t.launches = 0;
         return MGR_OK;
-    } catch (const Fail &f) {
-        return f.code;
+    } catch (...) {
+        return abi_status(h);
     }
 }
 
