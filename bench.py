@@ -193,6 +193,7 @@ def run_newton(dev, cfg, steps, warmup):
     return dict(ms_per_step=1e3 * dt, unknowns_per_s=pr.n / dt, newton_steps=len(res.steps) - 1,
                 converged=res.converged, rel_error_vs_u_star=err,
                 linear_iterations=[s.lin_iterations for s in res.steps[1:]],
+                values_only_updates=sum(1 for s in res.steps[1:] if s.values_only),
                 active_cells=[s.nactive for s in res.steps],
                 setup_ms=sum(s.setup_ms for s in res.steps), solve_ms=sum(s.solve_ms for s in res.steps),
                 workload=f"config {cfg} grid {'x'.join(map(str, p['grid']))} ({pr.n} unknowns): semi-smooth Newton "

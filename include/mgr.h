@@ -121,6 +121,23 @@ int mgr_setup(const mgr_csr *A, int block_size, const int32_t *cf_labels, const 
               mgr_handle **out);
 
 /*
+ * New values on the handle's matrix, with the pattern and cf_labels of its
+ * setup unchanged (the semi-smooth Newton iteration of Section 3.1 between
+ * steps whose active set, and so the Jacobian's pattern, did not change).
+ * Only the values are redone: D_FF^{-1}, W_p and W_r, the reduced operators
+ * A_{l+1} = R_l A_l P_l written over their arrays, the cell-block inverses, and
+ * the AMG hierarchies, rebuilt because their coarsening depends on the values.
+ * The pattern checks, level maps, sparsity patterns and Krylov workspace of the
+ * setup are kept.  The result is bitwise the one a new mgr_setup with these
+ * values would give.
+ *  values : device double[nnz] in the order of the setup's col_idx (copied).
+ * Errors: MGR_E_INVALID, MGR_E_ZERO_FDIAG, MGR_E_SINGULAR_BLOCK, MGR_E_HIP,
+ * MGR_E_OOM.  After an error the handle's hierarchy is incomplete: destroy it.
+ * The caller keeps the pattern unchanged; nothing checks it.
+ */
+int mgr_update_values(mgr_handle *h, const double *values);
+
+/*
  * Solve A x = b (or A^T x = b for a transpose handle) to
  * ||b - A x|| <= tol ||b|| with restarted right-preconditioned GMRES(m)
  * (Saad and Schultz 1986; the preconditioned directions are kept, x += Z y).
@@ -205,7 +222,10 @@ int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launch
  * the PDE rows; min(F, G) on the S rows] (step 1's residual) and labels for
  * mgr_setup: 3 for p, 1 for rho, and for S 2 on the active set A = {F >= G}
  * (the gas-present rows, zero diagonal) and 0 off it (the three-stage reduction of
- * Section 5).  *rnorm = ||R||_2, *nactive = |A| (host outputs, may be NULL).  All
+ * Section 5).  *rnorm = ||R||_2, *nactive = |A|, *nchanged = the number of cells
+ * whose labels differ from what the labels array held before the call (0: the
+ * Jacobian keeps its pattern, and mgr_update_values may replace a new setup);
+ * host outputs, each may be NULL.  All
  * arrays are caller-owned device memory of length n (henry: N); ordered on stream
  * (a hipStream_t); synchronises before returning.  Errors: MGR_E_INVALID (bad CSR
  * or null array), MGR_E_BREAKDOWN (non-finite residual), MGR_E_HIP, MGR_E_OOM.
@@ -219,7 +239,7 @@ int mgr_kernel_time(mgr_handle *h, int kernel, double *total_ms, int64_t *launch
  * suffices.  Ordered on stream; synchronises before returning.
  */
 int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double *u, const double *du, double alpha,
-                 double *R, int32_t *labels, double *rnorm, int64_t *nactive, void *stream);
+                 double *R, int32_t *labels, double *rnorm, int64_t *nactive, int64_t *nchanged, void *stream);
 int mgr_ncp_jacobian(const mgr_csr *L, const double *henry, const int32_t *labels, int32_t *row_ptr,
                      int32_t *col_idx, double *values, int64_t capacity, int64_t *nnz, void *stream);
 

@@ -6,7 +6,8 @@
 // Residual: the PDE rows R = L u - f (row sums in ascending column order), the
 // constraint row R = min(F, G) with F = S and G = rho - H p.  Active set
 // A = {c : F_c >= G_c}; its constraint row is G' = [-H, 1, 0], the inactive one
-// F' = [0, 0, 1].  Labels: p -> 3, rho -> 1, S -> 2 on A and 0 off A.
+// F' = [0, 0, 1].  Labels: p -> 3, rho -> 1, S -> 2 on A and 0 off A; the
+// evaluation counts the cells whose labels it changed.
 #include "mgr_impl.h"
 
 namespace mgr {
@@ -26,9 +27,9 @@ __global__ void __launch_bounds__(BT) k_ncp_eval(int64_t ncell, const int32_t *_
                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                  const double *__restrict__ henry, const double *__restrict__ f,
                                                  const double *__restrict__ u, double *__restrict__ R,
-                                                 int32_t *__restrict__ labels, int *nactive) {
+                                                 int32_t *__restrict__ labels, int *nactive, int *nchanged) {
     const int64_t c = gtid();
-    int act = 0;
+    int act = 0, chg = 0;
     if (c < ncell) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -41,13 +42,19 @@ __global__ void __launch_bounds__(BT) k_ncp_eval(int64_t ncell, const int32_t *_
         const double G = u[3 * c + 1] - henry[c] * u[3 * c];
         act = F >= G;
         R[3 * c + 2] = act ? G : F;
+        // the cell's labels before this evaluation (the Jacobian's pattern follows them)
+        chg = labels[3 * c] != 3 || labels[3 * c + 1] != 1 || labels[3 * c + 2] != (act ? 2 : 0);
         labels[3 * c] = 3;
         labels[3 * c + 1] = 1;
         labels[3 * c + 2] = act ? 2 : 0;
     }
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) act += __shfl_xor(act, o);
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        act += __shfl_xor(act, o);
+        chg += __shfl_xor(chg, o);
+    }
     if ((threadIdx.x & (kWave - 1)) == 0 && act) atomicAdd(nactive, act);
+    if ((threadIdx.x & (kWave - 1)) == 0 && chg) atomicAdd(nchanged, chg);
 }
 
 __global__ void k_ncp_jac_count(int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ labels,
@@ -89,8 +96,10 @@ void launch_axpy_inplace(int64_t n, double alpha, const double *du, double *u, h
     if (n > 0) k_axpy_inplace<<<nblocks(n, BT), BT, 0, s>>>(n, alpha, du, u);
 }
 void launch_ncp_eval(int64_t ncell, const int32_t *rp, const int32_t *ci, const double *v, const double *henry,
-                     const double *f, const double *u, double *R, int32_t *labels, int *nactive, hipStream_t s) {
-    if (ncell > 0) k_ncp_eval<<<nblocks(ncell, BT), BT, 0, s>>>(ncell, rp, ci, v, henry, f, u, R, labels, nactive);
+                     const double *f, const double *u, double *R, int32_t *labels, int *nactive, int *nchanged,
+                     hipStream_t s) {
+    if (ncell > 0)
+        k_ncp_eval<<<nblocks(ncell, BT), BT, 0, s>>>(ncell, rp, ci, v, henry, f, u, R, labels, nactive, nchanged);
 }
 void launch_ncp_jac_count(int64_t n, const int32_t *rp, const int32_t *labels, int32_t *cnt, hipStream_t s) {
     if (n > 0) k_ncp_jac_count<<<nblocks(n, BT), BT, 0, s>>>(n, rp, labels, cnt);

@@ -124,6 +124,16 @@ struct ScratchScope {
     ScratchScope &operator=(const ScratchScope &) = delete;
 };
 
+// handle-lifetime allocations of a scope go to the value-dependent `amg` arena
+struct AmgArenaScope {
+    mgr_handle *h;
+    mgr_handle::Arena *prev;
+    explicit AmgArenaScope(mgr_handle *hh) : h(hh), prev(hh->live) { hh->live = &hh->amg; }
+    ~AmgArenaScope() { h->live = prev; }
+    AmgArenaScope(const AmgArenaScope &) = delete;
+    AmgArenaScope &operator=(const AmgArenaScope &) = delete;
+};
+
 // temporary device buffer in the scratch arena
 template <typename T>
 struct Tmp {
@@ -179,12 +189,14 @@ int choose_lanes(const DCsr &A) {
     return 32;
 }
 
+// lanes per output row: the smallest group whose 8 chunks hold A's longest row
+int spgemm_group(int maxlen) { return maxlen <= 64 ? 8 : maxlen <= 128 ? 16 : maxlen <= 256 ? 32 : 64; }
+
 DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     DCsr C;
     C.nrows = A.nrows;
     C.ncols = B.ncols;
     Tmp<int32_t> cnt(h, A.nrows);
-    // lanes per output row: the smallest group whose 8 chunks hold A's longest row
     reset_err(h);
     launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
     read_err(h);
@@ -192,7 +204,7 @@ DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     if (maxlen > spgemm_max_row())
         throw_err(h, MGR_E_INVALID,
                   "SpGEMM: a left-operand row exceeds " + std::to_string(spgemm_max_row()) + " entries");
-    const int group = maxlen <= 64 ? 8 : maxlen <= 128 ? 16 : maxlen <= 256 ? 32 : 64;
+    const int group = spgemm_group(maxlen);
     reset_err(h);
     launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
                   h->stream);
@@ -224,6 +236,31 @@ DCsr transpose(mgr_handle *h, const DCsr &A, bool values, bool scratch = false) 
     return T;
 }
 
+// C = A B into C's arrays, whose pattern an earlier product of the same two
+// patterns produced: the value (fill) pass only
+void spgemm_values(mgr_handle *h, const DCsr &A, const DCsr &B, DCsr &C) {
+    reset_err(h);
+    launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
+    read_err(h);
+    reset_err(h);
+    launch_spgemm(1, spgemm_group(h->herr[1]), A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v,
+                  h->derr + 6, h->stream);
+    read_err(h);
+    if (h->herr[6]) throw_err(h, MGR_E_INVALID, "SpGEMM: row length check failed");
+}
+
+// T = A^T into T's arrays, built earlier from the same pattern (new values)
+void transpose_values(mgr_handle *h, const DCsr &A, DCsr &T) {
+    ScratchScope scope(h);
+    Tmp<int32_t> cnt(h, A.ncols);
+    launch_fill_i32(cnt.p, 0, A.ncols, h->stream);
+    launch_transpose_count(A.nrows, A.rp, A.ci, cnt.p, h->stream);
+    scan(h, cnt.p, T.rp, A.ncols);
+    HIPCHK(hipMemcpyAsync(cnt.p, T.rp, A.ncols * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+    launch_transpose_fill(A.nrows, A.rp, A.ci, A.v, cnt.p, T.ci, T.v, h->stream);
+    launch_transpose_sort(A.ncols, T.rp, T.ci, T.v, h->stream);
+}
+
 void build_csell(mgr_handle *h) {
     CSell &S = h->A0s;
     const DCsr &A = h->A0;
@@ -247,22 +284,11 @@ void build_csell(mgr_handle *h) {
 
 void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post);
 
-void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int32_t *&glob_next) {
+// D_FF^{-1} of MGR level l (its inverted F diagonal); a zero diagonal is an error
+// naming the row.  Leaves the "A_FF has off-diagonal entries" flag in herr[5].
+void fdiag_inverse(mgr_handle *h, int l) {
     MgrLevel &lv = h->lev[l];
     const DCsr &A = lv.A;
-    const int64_t n = A.nrows;
-    lv.n = n;
-    ScratchScope scope(h);
-    Tmp<int32_t> isF(h, n), isC(h, n), fpos(h, n + 1), cpos(h, n + 1), cmap(h, n);
-    launch_level_flags(n, lv.lab, l, isF.p, isC.p, h->stream);
-    lv.nF = scan(h, isF.p, fpos.p, n);
-    lv.nC = scan(h, isC.p, cpos.p, n);
-    if (lv.nC == 0) throw_err(h, MGR_E_INVALID, "MGR level " + std::to_string(l) + " has no coarse points");
-    lv.fmap = dalloc<int32_t>(h, n);
-    lv.flist = dalloc<int32_t>(h, lv.nF);
-    lv.clist = dalloc<int32_t>(h, lv.nC);
-    launch_level_maps(n, lv.lab, l, fpos.p, cpos.p, lv.fmap, cmap.p, lv.flist, lv.clist, h->stream);
-    lv.dinv = dalloc<double>(h, lv.nF);
     reset_err(h);
     launch_fdiag_inverse(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.dinv, h->derr, h->derr + 5, lv.fmap, h->stream);
     read_err(h);
@@ -273,6 +299,26 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
         std::snprintf(msg, sizeof msg, "MGR level %d: zero diagonal at F row %d (global unknown %d)", l, row, g);
         throw_err(h, MGR_E_ZERO_FDIAG, msg);
     }
+}
+
+void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int32_t *&glob_next) {
+    MgrLevel &lv = h->lev[l];
+    const DCsr &A = lv.A;
+    const int64_t n = A.nrows;
+    lv.n = n;
+    ScratchScope scope(h);
+    Tmp<int32_t> isF(h, n), isC(h, n), fpos(h, n + 1), cpos(h, n + 1);
+    lv.cmap = dalloc<int32_t>(h, n);
+    launch_level_flags(n, lv.lab, l, isF.p, isC.p, h->stream);
+    lv.nF = scan(h, isF.p, fpos.p, n);
+    lv.nC = scan(h, isC.p, cpos.p, n);
+    if (lv.nC == 0) throw_err(h, MGR_E_INVALID, "MGR level " + std::to_string(l) + " has no coarse points");
+    lv.fmap = dalloc<int32_t>(h, n);
+    lv.flist = dalloc<int32_t>(h, lv.nF);
+    lv.clist = dalloc<int32_t>(h, lv.nC);
+    launch_level_maps(n, lv.lab, l, fpos.p, cpos.p, lv.fmap, lv.cmap, lv.flist, lv.clist, h->stream);
+    lv.dinv = dalloc<double>(h, lv.nF);
+    fdiag_inverse(h, l);
     lv.aff_diag = h->herr[5] == 0;
     // compact copy of the F rows (all columns) for the F-point residual and the
     // in-place F-relaxation, at the levels whose cycle uses them
@@ -299,21 +345,23 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
         Aff.ci = dalloc<int32_t>(h, Aff.nnz);
         Aff.v = dalloc<double>(h, Aff.nnz);
         launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, Aff.rp, Aff.ci, Aff.v, h->stream);
+        lv.Aff = Aff;
         lv.ff = std::make_shared<AmgHier>();
+        AmgArenaScope amg_arena(h);
         build_amg(h, *lv.ff, Aff, h->o.frelax_amg_pre, h->o.frelax_amg_post);
     }
     const int rp_type = h->o.rp_type;
     // P = [W_p; I]
     {
         Tmp<int32_t> cnt(h, n);
-        launch_p_count(n, A.rp, A.ci, cmap.p, rp_type, cnt.p, h->stream);
+        launch_p_count(n, A.rp, A.ci, lv.cmap, rp_type, cnt.p, h->stream);
         lv.P.nrows = n;
         lv.P.ncols = lv.nC;
         lv.P.rp = dalloc<int32_t>(h, n + 1);
         lv.P.nnz = scan(h, cnt.p, lv.P.rp, n);
         lv.P.ci = dalloc<int32_t>(h, lv.P.nnz);
         lv.P.v = dalloc<double>(h, lv.P.nnz);
-        launch_p_fill(n, A.rp, A.ci, A.v, cmap.p, lv.fmap, lv.dinv, rp_type, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
+        launch_p_fill(n, A.rp, A.ci, A.v, lv.cmap, lv.fmap, lv.dinv, rp_type, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
     }
     // R = [W_r, I]
     {
@@ -428,9 +476,10 @@ float *to_f32(mgr_handle *h, const double *v, int64_t n) {
     return f;
 }
 
-void alloc_work(mgr_handle *h) {
+// V-cycle work vectors; `update`: the MGR-level ones exist, the AMG ones are new
+void alloc_work(mgr_handle *h, bool update = false) {
     const bool mixed = h->o.precision == 1;
-    for (size_t l = 0; l < h->lev.size(); ++l) {
+    for (size_t l = 0; l < h->lev.size() && !update; ++l) {
         MgrLevel &lv = h->lev[l];
         if (mixed) {
             lv.rf = dalloc<float>(h, lv.n);
@@ -443,6 +492,7 @@ void alloc_work(mgr_handle *h) {
         }
     }
     auto amg_work = [&](AmgHier &H) {
+        AmgArenaScope amg_arena(h);
         for (auto &lv : H.lev) {
             if (mixed) {
                 lv.rf = dalloc<float>(h, lv.n);
@@ -463,6 +513,7 @@ void alloc_work(mgr_handle *h) {
 }
 
 void amg_to_mixed(mgr_handle *h, AmgHier &H) {
+    AmgArenaScope amg_arena(h);
     for (size_t k = 0; k + 1 < H.lev.size(); ++k) {
         AmgLevel &lv = H.lev[k];
         lv.A.vf = to_f32(h, lv.A.v, lv.A.nnz);
@@ -472,15 +523,21 @@ void amg_to_mixed(mgr_handle *h, AmgHier &H) {
     }
 }
 
-void to_mixed(mgr_handle *h) {
-    if (h->binv) h->binvf = to_f32(h, h->binv, h->ncell * h->bs * h->bs);
-    h->A0s.vf = to_f32(h, h->A0s.v, h->A0s.nslot * kWave);
+// FP32 copies of the hierarchy's values; `update`: the MGR-level copies exist
+// (rewritten in place), the AMG ones belong to freshly built hierarchies
+void to_mixed(mgr_handle *h, bool update = false) {
+    auto cast = [&](float *&f, const double *v, int64_t n) {
+        if (update) launch_cast_f64_f32(v, f, n, h->stream);
+        else f = to_f32(h, v, n);
+    };
+    if (h->binv) cast(h->binvf, h->binv, h->ncell * h->bs * h->bs);
+    cast(h->A0s.vf, h->A0s.v, h->A0s.nslot * kWave);
     for (auto &lv : h->lev) {
-        lv.A.vf = to_f32(h, lv.A.v, lv.A.nnz);
-        lv.P.vf = to_f32(h, lv.P.v, lv.P.nnz);
-        lv.R.vf = to_f32(h, lv.R.v, lv.R.nnz);
-        if (lv.AF.v) lv.AF.vf = to_f32(h, lv.AF.v, lv.AF.nnz);
-        lv.dinvf = to_f32(h, lv.dinv, lv.nF);
+        cast(lv.A.vf, lv.A.v, lv.A.nnz);
+        cast(lv.P.vf, lv.P.v, lv.P.nnz);
+        cast(lv.R.vf, lv.R.v, lv.R.nnz);
+        if (lv.AF.v) cast(lv.AF.vf, lv.AF.v, lv.AF.nnz);
+        cast(lv.dinvf, lv.dinv, lv.nF);
         if (lv.ff) amg_to_mixed(h, *lv.ff);
     }
     amg_to_mixed(h, h->cg);
@@ -941,6 +998,7 @@ void pinned_put(void *p) {
 void destroy_impl(mgr_handle *h) {
     if (!h) return;
     arena_release(h, h->scratch);
+    arena_release(h, h->amg);
     arena_release(h, h->keep);
     (void)hipStreamSynchronize(h->stream);
     for (auto &t : h->tm)
@@ -967,6 +1025,69 @@ int check_options(const mgr_options *o, std::string &why) {
     else if (o->cycle_post != 0 && o->cycle_post != 1) why = "cycle_post must be 0 or 1";
     else return MGR_OK;
     return MGR_E_INVALID;
+}
+
+// Value update of MGR level l (same pattern and labels as at setup): D_FF^{-1},
+// the F-row copies, W_p and W_r in P and R, and A_{l+1} = R (A P), each written
+// over its arrays (the patterns, level maps and row pointers are kept); the AMG
+// F-relaxation hierarchy on A_FF is built anew, since its coarsening depends on
+// the values.  The same kernels as the setup, in the same order: the result is
+// bitwise the setup's.
+void update_mgr_level(mgr_handle *h, int l, DCsr &Anext) {
+    MgrLevel &lv = h->lev[l];
+    const DCsr &A = lv.A;
+    ScratchScope scope(h);
+    fdiag_inverse(h, l);
+    if (lv.AF.v) launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
+    if (lv.Aff.v) {  // the level relaxes its F points with an AMG cycle on A_FF
+        launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, lv.Aff.rp, lv.Aff.ci, lv.Aff.v, h->stream);
+        lv.ff = std::make_shared<AmgHier>();
+        AmgArenaScope amg_arena(h);
+        build_amg(h, *lv.ff, lv.Aff, h->o.frelax_amg_pre, h->o.frelax_amg_post);
+    }
+    const int rp_type = h->o.rp_type;
+    launch_p_fill(lv.n, A.rp, A.ci, A.v, lv.cmap, lv.fmap, lv.dinv, rp_type, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
+    launch_r_fill(lv.nC, lv.clist, A.rp, A.ci, A.v, lv.fmap, lv.dinv, rp_type, lv.R.rp, lv.R.ci, lv.R.v,
+                  h->stream);
+    DCsr T = spgemm(h, A, lv.P, true);
+    spgemm_values(h, lv.R, T, Anext);
+}
+
+// New values on the setup's pattern and labels: everything that depends only on
+// them (the validated pattern, level maps, sliced-ELL layout, the patterns of
+// P, R, the F-row copies and the reduced operators, the Krylov workspace) is
+// kept; the values are recomputed in place, and the AMG hierarchies are built
+// anew in their own arena.
+void update_impl(mgr_handle *h, const double *values) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = h->stream;
+    if (h->Ain.nnz > 0)
+        HIPCHK(hipMemcpyAsync(h->Ain.v, values, h->Ain.nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (h->o.transpose) transpose_values(h, h->Ain, h->A0);
+    const CSell &S = h->A0s;
+    launch_csell_fill(S.ncell, S.bs, h->A0.rp, h->A0.ci, h->A0.v, S.off, S.width, S.col, S.v, s);
+    if (h->binv) {
+        reset_err(h);
+        launch_block_inverse(h->ncell, h->bs, h->A0.rp, h->A0.ci, h->A0.v, h->binv, h->derr, s);
+        read_err(h);
+        if (h->herr[3] != INT_MAX)
+            throw_err(h, MGR_E_SINGULAR_BLOCK, "singular diagonal cell block at cell " + std::to_string(h->herr[3]));
+    }
+    // the previous AMG hierarchies (stream-ordered release: every kernel that
+    // reads them is queued before the kernels that reuse the memory)
+    for (auto &lv : h->lev) lv.ff.reset();
+    h->cg = AmgHier();
+    arena_release(h, h->amg);
+    for (int l = 0; l < h->L; ++l) update_mgr_level(h, l, l + 1 < h->L ? h->lev[l + 1].A : h->AL);
+    {
+        AmgArenaScope amg_arena(h);
+        build_amg(h, h->cg, h->AL, h->o.amg_pre, h->o.amg_post);
+    }
+    if (h->o.precision == 1) to_mixed(h, true);
+    alloc_work(h, true);
+    arena_release(h, h->scratch);
+    sync(h);
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_options *opts, mgr_handle **out) {
@@ -1055,7 +1176,11 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
             build_mgr_level(h, l, An, lab, glob);
             Acur = An;
         }
-        build_amg(h, h->cg, Acur, opts->amg_pre, opts->amg_post);
+        h->AL = Acur;
+        {
+            AmgArenaScope amg_arena(h);
+            build_amg(h, h->cg, Acur, opts->amg_pre, opts->amg_post);
+        }
         if (h->o.precision == 1) to_mixed(h);
         alloc_work(h);
         const int m = h->m;
@@ -1121,7 +1246,7 @@ int pool_alloc(mgr_handle *h, void **p, size_t bytes) {
 
 int alloc(mgr_handle *h, void **p, size_t bytes) {
     try {
-        *p = arena_alloc(h, h->keep, bytes);
+        *p = arena_alloc(h, h->live ? *h->live : h->keep, bytes);
         return MGR_OK;
     } catch (...) {
         *p = nullptr;
@@ -1163,6 +1288,20 @@ int mgr_setup(const mgr_csr *A, int block_size, const int32_t *cf_labels, const 
         return MGR_E_INVALID;
     }
     return setup_impl(A, block_size, cf_labels, opts, out);
+}
+
+int mgr_update_values(mgr_handle *h, const double *values) {
+    if (!h || (h->Ain.nnz > 0 && !values)) {
+        g_err = "invalid update arguments";
+        if (h) h->err = g_err;
+        return MGR_E_INVALID;
+    }
+    try {
+        update_impl(h, values);
+        return MGR_OK;
+    } catch (...) {
+        return abi_status(h);
+    }
 }
 
 int mgr_solve(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) {
@@ -1345,7 +1484,7 @@ static int check_ncp_csr(const mgr_csr *L) {
 }
 
 int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double *u, const double *du, double alpha,
-                 double *R, int32_t *labels, double *rnorm, int64_t *nactive, void *stream) {
+                 double *R, int32_t *labels, double *rnorm, int64_t *nactive, int64_t *nchanged, void *stream) {
     if (check_ncp_csr(L) != MGR_OK) return MGR_E_INVALID;
     if (!henry || !f || !u || !R || !labels) {
         g_err = "null argument";
@@ -1358,19 +1497,21 @@ int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double 
     try {
         const int64_t n = L->n, ncell = n / 3;
         if (du) launch_axpy_inplace(n, alpha, du, u, h->stream);
-        Tmp<int> cnt(h, 1);
-        launch_fill_i32(cnt.p, 0, 1, h->stream);
-        launch_ncp_eval(ncell, L->row_ptr, L->col_idx, L->values, henry, f, u, R, labels, cnt.p, h->stream);
+        Tmp<int> cnt(h, 2);  // active cells, cells whose labels changed
+        launch_fill_i32(cnt.p, 0, 2, h->stream);
+        launch_ncp_eval(ncell, L->row_ptr, L->col_idx, L->values, henry, f, u, R, labels, cnt.p, cnt.p + 1,
+                        h->stream);
         Tmp<double> part(h, kRedBlocks + 1);
         launch_norm_part(n, R, part.p, h->stream);
         launch_norm_fin(red_blocks(n), part.p, part.p + kRedBlocks, h->stream);
         double rn = 0.0;
-        int na = 0;
+        int na[2] = {0, 0};
         HIPCHK(hipMemcpyAsync(&rn, part.p + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(&na, cnt.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(na, cnt.p, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
         sync(h);
         if (rnorm) *rnorm = rn;
-        if (nactive) *nactive = na;
+        if (nactive) *nactive = na[0];
+        if (nchanged) *nchanged = na[1];
         return std::isfinite(rn) ? MGR_OK : MGR_E_BREAKDOWN;
     } catch (...) {
         return abi_status(nullptr);

@@ -63,9 +63,11 @@ struct MgrLevel {
     int32_t *lab = nullptr, *glob = nullptr;
     double *dinv = nullptr;
     float *dinvf = nullptr;
+    int32_t *cmap = nullptr;  // level row -> coarse index (-1 on F points)
     bool aff_diag = false;  // A_FF diagonal: the F-relaxation may update in place
     DCsr AF;                // compact copy of the F rows (all columns), row f = level row flist[f]
     int flanes = 1;         // threads per F row in the F-point residual / relaxation kernels
+    DCsr Aff;                     // A_FF (level 0 of ff), kept with the pattern-bound data
     std::shared_ptr<AmgHier> ff;  // AMG V-cycle on A_FF as the F-relaxation (else Jacobi)
     // V-cycle work vectors
     double *e = nullptr, *t = nullptr, *r = nullptr;
@@ -80,14 +82,18 @@ struct mgr_handle {
     int64_t n = 0, ncell = 0;
     int bs = 1, L = 0;
     std::string err;
-    // device memory: `keep` holds what lives as long as the handle, `scratch` the
-    // temporaries of one call (released when the call returns)
+    // device memory: `keep` holds what lives as long as the handle and depends on
+    // the pattern and labels only (plus the value arrays of the MGR levels, which
+    // a value update rewrites in place), `amg` the AMG hierarchies and their work
+    // vectors (their coarsening depends on the values: rebuilt on a value
+    // update), `scratch` the temporaries of one call (released when it returns)
     struct Arena {
         std::vector<void *> chunks;
         char *cur = nullptr;
         size_t left = 0;
     };
-    Arena keep, scratch;
+    Arena keep, scratch, amg;
+    Arena *live = nullptr;  // where handle-lifetime allocations go (null: keep)
 
     mgr::DCsr Ain;   // the matrix as passed (pattern of mgr_pattern_outer)
     mgr::DCsr A0;    // level-0 operator (A or A^T)
@@ -95,6 +101,7 @@ struct mgr_handle {
     double *binv = nullptr;  // 9 planes of ncell (bs = 3) or 1 plane (bs = 1)
     float *binvf = nullptr;
     std::vector<mgr::MgrLevel> lev;
+    mgr::DCsr AL;     // the last reduction level's matrix (level 0 of cg)
     mgr::AmgHier cg;  // coarse-grid AMG on the last reduction level
 
     // Krylov workspace
@@ -255,7 +262,8 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
 // ---- semi-smooth Newton support (k_ncp.hip) ----
 void launch_axpy_inplace(int64_t n, double alpha, const double *du, double *u, hipStream_t s);
 void launch_ncp_eval(int64_t ncell, const int32_t *rp, const int32_t *ci, const double *v, const double *henry,
-                     const double *f, const double *u, double *R, int32_t *labels, int *nactive, hipStream_t s);
+                     const double *f, const double *u, double *R, int32_t *labels, int *nactive, int *nchanged,
+                     hipStream_t s);
 void launch_ncp_jac_count(int64_t n, const int32_t *rp, const int32_t *labels, int32_t *cnt, hipStream_t s);
 void launch_ncp_jac_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const double *henry,
                          const int32_t *labels, const int32_t *Jrp, int32_t *Jci, double *Jv, hipStream_t s);

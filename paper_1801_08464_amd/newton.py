@@ -2,8 +2,10 @@
 Method") around the MGR-GMRES solver, for the complementarity system with
 unknowns (p, rho, S) per cell.  Argument marshalling only: the residual, the
 active set, the labels, the generalised Jacobian and the update run in the
-library (mgr_ncp_eval, mgr_ncp_jacobian); each step builds a hierarchy for its
-Jacobian and labels (mgr_setup) and solves J x = R (mgr_solve), then u -= x.
+library (mgr_ncp_eval, mgr_ncp_jacobian); each step solves J x = R with
+MGR-GMRES (mgr_solve), then u -= x.  A step whose labels (active set) are those
+of the hierarchy's setup keeps the Jacobian's pattern, so the hierarchy takes
+the new values only (mgr_update_values); otherwise it is set up anew (mgr_setup).
 """
 from __future__ import annotations
 
@@ -25,6 +27,7 @@ class NewtonStep:
     lin_status: int = 0
     setup_ms: float = 0.0
     solve_ms: float = 0.0
+    values_only: bool = False  # the hierarchy took new values on its setup's pattern
 
 
 @dataclass
@@ -65,13 +68,15 @@ class NCPNewton:
 
     def eval(self, u, du=None, alpha=1.0):
         """u += alpha du (if du is given), then R(u) and the labels; returns
-        (||R||, |A|).  u is updated in place."""
-        rn, na = C.c_double(), C.c_int64()
+        (||R||, |A|).  u is updated in place; self.nchanged is the number of
+        cells whose labels the call changed."""
+        rn, na, nch = C.c_double(), C.c_int64(), C.c_int64()
         rc = self.lib.mgr_ncp_eval(C.byref(self.csr), _ptr(self.henry), _ptr(self.f), _ptr(u),
                                    _ptr(du) if du is not None else None, float(alpha), _ptr(self.R),
-                                   _ptr(self.labels), C.byref(rn), C.byref(na), self._stream())
+                                   _ptr(self.labels), C.byref(rn), C.byref(na), C.byref(nch), self._stream())
         if rc != B.OK:
             raise B.MGRError(rc, B.last_error(None))
+        self.nchanged = nch.value
         return rn.value, na.value
 
     def jacobian(self):
@@ -93,14 +98,25 @@ class NCPNewton:
         r0, na = self.eval(u)
         steps = [NewtonStep(r0, na)]
         rn = r0
-        for _ in range(max_newton):
-            if rn <= tol * r0:
-                break
-            rp, ci, vals = self.jacobian()
-            g = MGRSolver(rp, ci, vals, self.labels, **solver_opts)
-            x, info = g.solve(self.R, lin_tol, history=False)
-            g.close()
-            rn, na = self.eval(u, x, -1.0)
-            steps.append(NewtonStep(rn, na, info.iterations, info.status, info.setup_ms, info.solve_ms))
+        g = None
+        try:
+            for _ in range(max_newton):
+                if rn <= tol * r0:
+                    break
+                rp, ci, vals = self.jacobian()
+                values_only = g is not None and self.nchanged == 0
+                if values_only:
+                    g.update_values(vals)
+                else:
+                    if g is not None:
+                        g.close()
+                    g = MGRSolver(rp, ci, vals, self.labels, **solver_opts)
+                x, info = g.solve(self.R, lin_tol, history=False)
+                rn, na = self.eval(u, x, -1.0)
+                steps.append(NewtonStep(rn, na, info.iterations, info.status, info.setup_ms, info.solve_ms,
+                                        values_only))
+        finally:
+            if g is not None:
+                g.close()
         torch.cuda.synchronize(self.device)
         return NewtonResult(u, rn <= tol * r0, steps, time.perf_counter() - t0)

@@ -97,6 +97,17 @@ class MGRSolver:
             raise B.MGRError(rc, B.last_error(self.h))
         return rc
 
+    def update_values(self, values):
+        """New values on the setup's pattern and labels (mgr_update_values): the
+        hierarchy's values are redone and its AMG parts rebuilt; the patterns,
+        level maps and workspace are kept.  The next solve's setup_ms is the
+        update's time."""
+        v = _dev(values, torch.float64, self.device)
+        if v.numel() != self.nnz:
+            raise ValueError(f"expected {self.nnz} values, got {v.numel()}")
+        self.values = v
+        self._check(self.lib.mgr_update_values(self.h, _ptr(self.values)))
+
     # ---- solves ----
     def solve(self, b, tol=1e-8, x0=None, history=True):
         b = _dev(b, torch.float64, self.device)

@@ -80,7 +80,7 @@ def test_jacobian_capacity_and_argument_errors(orc):
     assert "capacity" in B.last_error(None)
     bad = B.MgrCsr(7, 0, g.csr.row_ptr, None, None)
     rc = g.lib.mgr_ncp_eval(C.byref(bad), g.henry.data_ptr(), g.f.data_ptr(), g.R.data_ptr(), None, 1.0,
-                            g.R.data_ptr(), g.labels.data_ptr(), None, None, stream)
+                            g.R.data_ptr(), g.labels.data_ptr(), None, None, None, stream)
     assert rc == B.E_INVALID
 
 
@@ -113,6 +113,8 @@ def test_newton_at_benchmark_size():
     prev = make_ncp_problem(p["grid"], p["sigma"], p["region"], 0.8 * p["frac"], p["seed"])
     print(f"[newton full] n={pr.n}", flush=True)
     res = _gpu(pr).solve(u0=prev.u_star, frelax_amg_mask=2)
+    print(f"[newton full] steps={len(res.steps) - 1} values-only updates="
+          f"{sum(s.values_only for s in res.steps[1:])}", flush=True)
     assert res.converged and len(res.steps) - 1 <= 10
     u = res.u.cpu().numpy()
     assert np.linalg.norm(u - pr.u_star) <= 1e-9 * np.linalg.norm(pr.u_star)

@@ -20,49 +20,53 @@ def compare_hierarchy(orc, s, **opts):
     o = orc.Oracle(oracle_csr(orc, s), s.labels, **opts)
     g = gpu_solver(s, **{k: v for k, v in opts.items() if k != "precision"})
     try:
-        nm, na = g.levels
-        assert (nm, na) == (o.n_mgr_levels, o.n_amg_levels)
-        if o.n_mgr_levels > 0 and opts.get("global_relax", 1):
-            np.testing.assert_array_equal(g.get_vector(0), o.block_inverses(), err_msg="cell-block inverses")
-        for l in range(nm):
-            ol = o.mgr_level(l)
-            assert_same_csr(g.get_matrix(0, l), ol["A"], f"MGR A_{l}")
-            assert_same_csr(g.get_matrix(1, l), ol["P"], f"MGR P_{l}")
-            assert_same_csr(g.get_matrix(2, l), ol["R"], f"MGR R_{l}")
-            np.testing.assert_array_equal(g.get_vector(1, l), ol["dinv"], err_msg=f"dinv_{l}")
-            np.testing.assert_array_equal(g.get_vector(2, l), ol["flist"], err_msg=f"F list {l}")
-            np.testing.assert_array_equal(g.get_vector(3, l), ol["clist"], err_msg=f"C list {l}")
-        for k in range(na):
-            ok = o.amg_level(k)
-            assert_same_csr(g.get_matrix(3, k), ok["A"], f"AMG A_{k}")
-            if k < na - 1:
-                np.testing.assert_array_equal(g.get_vector(4, k), ok["cf"], err_msg=f"AMG C/F split {k}")
-                assert_same_csr(g.get_matrix(5, k), ok["S"], f"AMG strength {k}")
-                assert_same_csr(g.get_matrix(4, k), ok["P"], f"AMG P_{k}")
-                np.testing.assert_array_equal(g.get_vector(5, k), ok["l1"], err_msg=f"AMG l1 {k}")
-        lu, perm = o.coarse_lu()
-        np.testing.assert_array_equal(g.get_vector(7), perm, err_msg="coarsest LU permutation")
-        np.testing.assert_array_equal(g.get_vector(6), lu.ravel(), err_msg="coarsest LU factors")
-        for l in range(nm):
-            nff = o.n_ff_levels(l)
-            for k in range(nff):
-                code = (l << 8) | k
-                ok = o.ff_level(l, k)
-                assert_same_csr(g.get_matrix(6, code), ok["A"], f"F-block AMG A_{k} of level {l}")
-                if k < nff - 1:
-                    assert_same_csr(g.get_matrix(7, code), ok["P"], f"F-block AMG P_{k} of level {l}")
-                    np.testing.assert_array_equal(g.get_vector(8, code), ok["cf"])
-                    np.testing.assert_array_equal(g.get_vector(9, code), ok["l1"])
-            if nff:
-                flu, fperm = o.ff_coarse_lu(l)
-                np.testing.assert_array_equal(g.get_vector(11, l << 8), fperm)
-                np.testing.assert_array_equal(g.get_vector(10, l << 8), flu.ravel())
-            else:
-                with pytest.raises(Exception):
-                    g.get_matrix(6, l << 8)
+        check_hierarchy(g, o, **opts)
     finally:
         g.close()
         o.close()
+
+
+def check_hierarchy(g, o, **opts):
+    nm, na = g.levels
+    assert (nm, na) == (o.n_mgr_levels, o.n_amg_levels)
+    if o.n_mgr_levels > 0 and opts.get("global_relax", 1):
+        np.testing.assert_array_equal(g.get_vector(0), o.block_inverses(), err_msg="cell-block inverses")
+    for l in range(nm):
+        ol = o.mgr_level(l)
+        assert_same_csr(g.get_matrix(0, l), ol["A"], f"MGR A_{l}")
+        assert_same_csr(g.get_matrix(1, l), ol["P"], f"MGR P_{l}")
+        assert_same_csr(g.get_matrix(2, l), ol["R"], f"MGR R_{l}")
+        np.testing.assert_array_equal(g.get_vector(1, l), ol["dinv"], err_msg=f"dinv_{l}")
+        np.testing.assert_array_equal(g.get_vector(2, l), ol["flist"], err_msg=f"F list {l}")
+        np.testing.assert_array_equal(g.get_vector(3, l), ol["clist"], err_msg=f"C list {l}")
+    for k in range(na):
+        ok = o.amg_level(k)
+        assert_same_csr(g.get_matrix(3, k), ok["A"], f"AMG A_{k}")
+        if k < na - 1:
+            np.testing.assert_array_equal(g.get_vector(4, k), ok["cf"], err_msg=f"AMG C/F split {k}")
+            assert_same_csr(g.get_matrix(5, k), ok["S"], f"AMG strength {k}")
+            assert_same_csr(g.get_matrix(4, k), ok["P"], f"AMG P_{k}")
+            np.testing.assert_array_equal(g.get_vector(5, k), ok["l1"], err_msg=f"AMG l1 {k}")
+    lu, perm = o.coarse_lu()
+    np.testing.assert_array_equal(g.get_vector(7), perm, err_msg="coarsest LU permutation")
+    np.testing.assert_array_equal(g.get_vector(6), lu.ravel(), err_msg="coarsest LU factors")
+    for l in range(nm):
+        nff = o.n_ff_levels(l)
+        for k in range(nff):
+            code = (l << 8) | k
+            ok = o.ff_level(l, k)
+            assert_same_csr(g.get_matrix(6, code), ok["A"], f"F-block AMG A_{k} of level {l}")
+            if k < nff - 1:
+                assert_same_csr(g.get_matrix(7, code), ok["P"], f"F-block AMG P_{k} of level {l}")
+                np.testing.assert_array_equal(g.get_vector(8, code), ok["cf"])
+                np.testing.assert_array_equal(g.get_vector(9, code), ok["l1"])
+        if nff:
+            flu, fperm = o.ff_coarse_lu(l)
+            np.testing.assert_array_equal(g.get_vector(11, l << 8), fperm)
+            np.testing.assert_array_equal(g.get_vector(10, l << 8), flu.ravel())
+        else:
+            with pytest.raises(Exception):
+                g.get_matrix(6, l << 8)
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -128,3 +132,58 @@ def test_setup_is_deterministic(orc):
     finally:
         a.close()
         b.close()
+
+
+def _perturbed(s, seed):
+    # the same pattern and labels with every value scaled by a factor in [0.85, 1.15]
+    f = 1.0 + 0.3 * (np.random.default_rng(seed).random(s.data.shape[0]) - 0.5)
+    return s.__class__(**{**s.__dict__, "data": s.data * f})
+
+
+def test_update_values_is_bitwise_a_new_setup(orc):
+    # values-only update (the Newton step with an unchanged active set): every
+    # hierarchy object equals the oracle's on the new values, and two updates
+    # in a row (new values, then the first ones back) each equal a fresh setup
+    s = small_system((13, 11, 9), seed=4, sigma=2.0, frac=0.3, region="ball")
+    s2 = _perturbed(s, 11)
+    g = gpu_solver(s, frelax_amg_mask=2)
+    try:
+        g.update_values(s2.data)
+        o = orc.Oracle(oracle_csr(orc, s2), s2.labels, frelax_amg_mask=2)
+        try:
+            check_hierarchy(g, o, frelax_amg_mask=2)
+        finally:
+            o.close()
+        for sys_ in (s2, s):
+            if sys_ is s:
+                g.update_values(s.data)
+            f = gpu_solver(sys_, frelax_amg_mask=2)
+            try:
+                xa, ia = g.solve(sys_.b, 1e-10)
+                xb, ib = f.solve(sys_.b, 1e-10)
+                assert ia.status == ib.status == 0 and ia.iterations == ib.iterations
+                np.testing.assert_array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+            finally:
+                f.close()
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("opts", [dict(precision="mixed"), dict(transpose=True), dict(frelax_amg_mask=6)])
+def test_update_values_forms(opts):
+    s = small_system((17, 15, 5), seed=6, sigma=1.5, frac=0.35, region="ball")
+    s2 = _perturbed(s, 12)
+    g = gpu_solver(s, **opts)
+    f = gpu_solver(s2, **opts)
+    try:
+        g.update_values(s2.data)
+        xa, ia = g.solve(s2.b, 1e-9)
+        xb, ib = f.solve(s2.b, 1e-9)
+        assert ia.status == ib.status == 0 and ia.iterations == ib.iterations
+        np.testing.assert_array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+        for k in range(g.levels[1]):
+            for x, y in zip(g.get_matrix(3, k)[:3], f.get_matrix(3, k)[:3]):
+                np.testing.assert_array_equal(x, y)
+    finally:
+        g.close()
+        f.close()
