@@ -334,7 +334,7 @@ def main():
     cs = main_form.get("coarse_sweep")
     # the dominant kernel of a step: the l1-Jacobi sweep on the coarse-grid matrix
     # (three launches per iteration); the fine-level operator is reported beside it
-    roof = roofline(cs, "k_csr_stream<double, 3, 256, 4096>: l1-Jacobi sweep on the coarse-grid matrix "
+    roof = roofline(cs, "k_csr_stream<double, 3, 256, 5120>: l1-Jacobi sweep on the coarse-grid matrix "
                         "(AMG level 0 of the pressure system)", SWEEP_RECORD, SWEEP_SOURCE,
                     args.config) if cs else None
     roof_fine = roofline(fk, "k_csell: level-0 sliced-ELL SpMV / residual (the GMRES operator)", FINE_RECORD,

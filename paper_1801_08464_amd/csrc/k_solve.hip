@@ -365,7 +365,8 @@ static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const
 // to 600k rows about 1 % more)
 constexpr int64_t kCsrStreamMinRows = 131072;
 // mean row lengths below which the stream kernel takes 1024- and 2048-entry passes
-// (above: 4096 entries in FP64, 8192 in FP32)
+// (above: 5120 entries in FP64, 20 per thread, 40 KB of LDS: 4 workgroups per CU;
+// 8192 in FP32)
 constexpr double kStreamShortRow = 3.0;
 constexpr double kStreamMidRow = 8.0;
 
@@ -379,8 +380,8 @@ static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T 
     if (A.nrows >= kCsrStreamMinRows) {
         if (avg < kStreamShortRow) csr_rows<T, 256, 1024>(mode, A, vals, x, r, d, y, y2, s);
         else if (avg < kStreamMidRow) csr_rows<T, 256, 2048>(mode, A, vals, x, r, d, y, y2, s);
-        else if (sizeof(T) == 4) csr_rows<T, 256, 8192>(mode, A, vals, x, r, d, y, y2, s);  // same LDS bytes
-        else csr_rows<T, 256, 4096>(mode, A, vals, x, r, d, y, y2, s);
+        else if (sizeof(T) == 4) csr_rows<T, 256, 8192>(mode, A, vals, x, r, d, y, y2, s);
+        else csr_rows<T, 256, 5120>(mode, A, vals, x, r, d, y, y2, s);
         return;
     }
     const int lanes = avg < 3 ? 2 : avg < 6 ? 4 : avg < 12 ? 8 : avg < 24 ? 16 : 32;
