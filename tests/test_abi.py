@@ -43,3 +43,8 @@ def test_host_only_entry_points():
     assert B.load_library().mgr_setup(ctypes.byref(csr), 3, None, ctypes.byref(o), ctypes.byref(h)) == B.E_INVALID
     assert not h.value
     assert B.last_error(None)
+    # the handle entry points reject a null handle before touching the device
+    L = B.load_library()
+    assert L.mgr_update_values(None, None) == B.E_INVALID
+    assert L.mgr_solve(None, None, None, 1e-8, None) == B.E_INVALID
+    assert L.mgr_apply_preconditioner(None, None, None) == B.E_INVALID
