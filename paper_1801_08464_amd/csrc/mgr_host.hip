@@ -69,24 +69,74 @@ T *dalloc(mgr_handle *h, int64_t n) {
 // Arenas: bump allocation in chunks taken from the stream-ordered pool.  Each
 // pool call costs tens of microseconds, and a hierarchy needs hundreds of
 // buffers, so buffers are carved out of 64 MiB chunks (a larger request gets a
-// chunk of its own) and released chunk by chunk.  Reuse is stream-ordered: a
-// kernel queued later on the stream runs after every earlier reader.
+// chunk of its own) and released chunk by chunk.  Released blocks are not given
+// back to the pool at once: the handle reuses them by exact size (in stream
+// order: a kernel queued later on the stream runs after every earlier reader),
+// and a destroyed handle, once its stream has drained, leaves them to a
+// per-device cache that later handles draw from.
 constexpr size_t kArenaChunk = size_t(64) << 20;
 constexpr size_t kArenaAlign = 256;
+constexpr size_t kBlockCacheMax = size_t(16) << 30;  // per device; beyond: back to the pool
+
+struct BlockCache {
+    std::multimap<size_t, void *> blocks;
+    size_t bytes = 0;
+};
+std::mutex g_block_mu;
+std::map<int, BlockCache> g_blocks;
+
+void *block_get(mgr_handle *h, size_t bytes) {
+    auto it = h->spare.find(bytes);
+    if (it != h->spare.end()) {
+        void *p = it->second;
+        h->spare.erase(it);
+        return p;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_block_mu);
+        auto c = g_blocks.find(dev);
+        if (c != g_blocks.end()) {
+            auto b = c->second.blocks.find(bytes);
+            if (b != c->second.blocks.end()) {
+                void *p = b->second;
+                c->second.blocks.erase(b);
+                c->second.bytes -= bytes;
+                return p;
+            }
+        }
+    }
+    void *p = nullptr;
+    if (pool_alloc(h, &p, bytes) != MGR_OK) throw_err(h, MGR_E_OOM, "device allocation failed");
+    return p;
+}
+
+// after the handle's stream has drained: its spare blocks go to the device cache
+void blocks_to_cache(mgr_handle *h) {
+    std::lock_guard<std::mutex> lk(g_block_mu);
+    BlockCache &c = g_blocks[h->device];
+    for (auto &b : h->spare) {
+        if (c.bytes + b.first <= kBlockCacheMax) {
+            c.blocks.emplace(b.first, b.second);
+            c.bytes += b.first;
+        } else {
+            (void)hipFreeAsync(b.second, h->stream);
+        }
+    }
+    h->spare.clear();
+}
 
 void *arena_alloc(mgr_handle *h, mgr_handle::Arena &a, size_t bytes) {
     bytes = (bytes + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
     if (bytes == 0) bytes = kArenaAlign;
     if (bytes > kArenaChunk / 4) {
-        void *p = nullptr;
-        if (pool_alloc(h, &p, bytes) != MGR_OK) throw_err(h, MGR_E_OOM, "device allocation failed");
-        a.chunks.push_back(p);
+        void *p = block_get(h, bytes);
+        a.chunks.emplace_back(p, bytes);
         return p;
     }
     if (bytes > a.left) {
-        void *p = nullptr;
-        if (pool_alloc(h, &p, kArenaChunk) != MGR_OK) throw_err(h, MGR_E_OOM, "device allocation failed");
-        a.chunks.push_back(p);
+        void *p = block_get(h, kArenaChunk);
+        a.chunks.emplace_back(p, kArenaChunk);
         a.cur = static_cast<char *>(p);
         a.left = kArenaChunk;
     }
@@ -106,7 +156,7 @@ ArenaMark arena_mark(const mgr_handle::Arena &a) { return {a.chunks.size(), a.cu
 
 // release every chunk taken after mark m and resume bump allocation where m was
 void arena_reset(mgr_handle *h, mgr_handle::Arena &a, const ArenaMark &m) {
-    for (size_t i = m.nchunks; i < a.chunks.size(); ++i) (void)hipFreeAsync(a.chunks[i], h->stream);
+    for (size_t i = m.nchunks; i < a.chunks.size(); ++i) h->spare.emplace(a.chunks[i].second, a.chunks[i].first);
     a.chunks.resize(m.nchunks);
     a.cur = m.cur;
     a.left = m.left;
@@ -995,12 +1045,22 @@ void pinned_put(void *p) {
     g_pinned_free.push_back(p);
 }
 
+}  // namespace
+
+// blocks still held (a handle that never reached the device cache, or the
+// temporary handle of a handle-free entry point): back to the pool, in order
+mgr_handle::~mgr_handle() {
+    for (auto &b : spare) (void)hipFreeAsync(b.second, stream);
+}
+
+namespace {
+
 void destroy_impl(mgr_handle *h) {
     if (!h) return;
     arena_release(h, h->scratch);
     arena_release(h, h->amg);
     arena_release(h, h->keep);
-    (void)hipStreamSynchronize(h->stream);
+    if (hipStreamSynchronize(h->stream) == hipSuccess) blocks_to_cache(h);
     for (auto &t : h->tm)
         for (auto e : t.ev) (void)hipEventDestroy(e);
     pinned_put(h->hsc);
@@ -1114,6 +1174,7 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
     try {
         auto t0 = std::chrono::steady_clock::now();
         h->stream = (hipStream_t)opts->stream;
+        HIPCHK(hipGetDevice(&h->device));
         h->o = *opts;
         h->n = Ain->n;
         h->bs = bs;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -88,12 +89,20 @@ struct mgr_handle {
     // vectors (their coarsening depends on the values: rebuilt on a value
     // update), `scratch` the temporaries of one call (released when it returns)
     struct Arena {
-        std::vector<void *> chunks;
+        std::vector<std::pair<void *, size_t>> chunks;  // device blocks and their sizes
         char *cur = nullptr;
         size_t left = 0;
     };
     Arena keep, scratch, amg;
     Arena *live = nullptr;  // where handle-lifetime allocations go (null: keep)
+    // blocks released by the arenas, reused by exact size in stream order;
+    // freed (stream-ordered) when the handle object goes away
+    std::multimap<size_t, void *> spare;
+    int device = 0;
+    mgr_handle() = default;
+    mgr_handle(const mgr_handle &) = delete;
+    mgr_handle &operator=(const mgr_handle &) = delete;
+    ~mgr_handle();
 
     mgr::DCsr Ain;   // the matrix as passed (pattern of mgr_pattern_outer)
     mgr::DCsr A0;    // level-0 operator (A or A^T)
