@@ -200,12 +200,16 @@ T *salloc(mgr_handle *h, int64_t n) {
     return static_cast<T *>(arena_alloc(h, h->scratch, (size_t)(n > 0 ? n : 1) * sizeof(T)));
 }
 
+// one device word to the host; through the handle's pinned block when it has
+// one (a pageable destination costs a staged copy)
 template <typename T>
 T d2h1(mgr_handle *h, const T *p) {
+    static_assert(sizeof(T) <= 8, "one word");
+    T *dst = h->hsc ? reinterpret_cast<T *>(reinterpret_cast<char *>(h->hsc) + 128) : nullptr;
     T v;
-    HIPCHK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(dst ? dst : &v, p, sizeof(T), hipMemcpyDeviceToHost, h->stream));
     sync(h);
-    return v;
+    return dst ? *dst : v;
 }
 
 void reset_err(mgr_handle *h) {
