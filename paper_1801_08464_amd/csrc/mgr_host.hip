@@ -223,12 +223,17 @@ void read_err(mgr_handle *h) {
     sync(h);
 }
 
-// exclusive scan of n counts into out[0..n]; returns the total (checked to fit int32)
-int64_t scan(mgr_handle *h, const int32_t *in, int32_t *out, int64_t n) {
+// exclusive scan of n counts into out[0..n]; returns the total (checked to fit
+// int32).  with_err: the device error words come back with the total (one
+// synchronisation for both)
+int64_t scan(mgr_handle *h, const int32_t *in, int32_t *out, int64_t n, bool with_err = false) {
     Tmp<int64_t> tmp(h, scan_tmp_words(n));
     launch_scan(in, out, n, tmp.p, h->stream);
     int64_t nt = (n + 2047) / 2048;
-    int64_t total = n > 0 ? d2h1(h, tmp.p + nt) : 0;
+    if (with_err) HIPCHK(hipMemcpyAsync(h->herr, h->derr, 8 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    int64_t total = 0;
+    if (n > 0) total = d2h1(h, tmp.p + nt);
+    else if (with_err) sync(h);
     if (total > INT_MAX) throw_err(h, MGR_E_INVALID, "a hierarchy matrix exceeds 2^31-1 entries");
     return total;
 }
@@ -263,8 +268,7 @@ DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
                   h->stream);
     C.rp = scratch ? salloc<int32_t>(h, A.nrows + 1) : dalloc<int32_t>(h, A.nrows + 1);
-    C.nnz = scan(h, cnt.p, C.rp, A.nrows);
-    read_err(h);
+    C.nnz = scan(h, cnt.p, C.rp, A.nrows, true);
     if (h->herr[6]) throw_err(h, MGR_E_INVALID, "SpGEMM: row length check failed");
     C.ci = scratch ? salloc<int32_t>(h, C.nnz) : dalloc<int32_t>(h, C.nnz);
     C.v = scratch ? salloc<double>(h, C.nnz) : dalloc<double>(h, C.nnz);
@@ -286,7 +290,6 @@ DCsr transpose(mgr_handle *h, const DCsr &A, bool values, bool scratch = false) 
     HIPCHK(hipMemcpyAsync(cnt.p, T.rp, A.ncols * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
     launch_transpose_fill(A.nrows, A.rp, A.ci, values ? A.v : nullptr, cnt.p, T.ci, T.v, h->stream);
     launch_transpose_sort(A.ncols, T.rp, T.ci, T.v, h->stream);
-    sync(h);
     return T;
 }
 
