@@ -328,8 +328,11 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
     if (row >= m) return;  // uniform per group
     const int a0 = Arp[row];
     const int len = Arp[row + 1] - a0;
-    if (len > G * kSpgChunks) {
-        if (glane == 0) atomicOr(err, 1);
+    if (len > G * kSpgChunks) {  // too long for this group size: flagged, counted as empty
+        if (glane == 0) {
+            atomicOr(err, 1);
+            if (!FILL) cnt_or_Crp[row] = 0;
+        }
         return;
     }
     const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1);

@@ -256,20 +256,30 @@ DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     C.nrows = A.nrows;
     C.ncols = B.ncols;
     Tmp<int32_t> cnt(h, A.nrows);
-    reset_err(h);
-    launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
-    read_err(h);
-    const int maxlen = h->herr[1];
-    if (maxlen > spgemm_max_row())
-        throw_err(h, MGR_E_INVALID,
-                  "SpGEMM: a left-operand row exceeds " + std::to_string(spgemm_max_row()) + " entries");
-    const int group = spgemm_group(maxlen);
+    C.rp = scratch ? salloc<int32_t>(h, A.nrows + 1) : dalloc<int32_t>(h, A.nrows + 1);
+    // count with the smallest group first; a row too long for it (the kernel's
+    // error word, read with the scan total) sends the count to the group that
+    // the longest row needs
+    int group = spgemm_group(0);
     reset_err(h);
     launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
                   h->stream);
-    C.rp = scratch ? salloc<int32_t>(h, A.nrows + 1) : dalloc<int32_t>(h, A.nrows + 1);
     C.nnz = scan(h, cnt.p, C.rp, A.nrows, true);
-    if (h->herr[6]) throw_err(h, MGR_E_INVALID, "SpGEMM: row length check failed");
+    if (h->herr[6]) {
+        reset_err(h);
+        launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
+        read_err(h);
+        const int maxlen = h->herr[1];
+        if (maxlen > spgemm_max_row())
+            throw_err(h, MGR_E_INVALID,
+                      "SpGEMM: a left-operand row exceeds " + std::to_string(spgemm_max_row()) + " entries");
+        group = spgemm_group(maxlen);
+        reset_err(h);
+        launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
+                      h->stream);
+        C.nnz = scan(h, cnt.p, C.rp, A.nrows, true);
+        if (h->herr[6]) throw_err(h, MGR_E_INVALID, "SpGEMM: row length check failed");
+    }
     C.ci = scratch ? salloc<int32_t>(h, C.nnz) : dalloc<int32_t>(h, C.nnz);
     C.v = scratch ? salloc<double>(h, C.nnz) : dalloc<double>(h, C.nnz);
     launch_spgemm(1, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v, h->derr + 6, h->stream);
@@ -475,10 +485,16 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
             lv.cf = dalloc<int32_t>(h, n);
             Tmp<int32_t> newc(h, n);
             launch_pmis_init(n, ST.rp, lv.cf, h->stream);
-            for (int round = 0;; ++round) {
-                reset_err(h);
-                launch_pmis_select(n, lv.S.rp, lv.S.ci, ST.rp, ST.ci, lv.cf, o.pmis_seed, newc.p, h->stream);
-                launch_pmis_update(n, lv.S.rp, lv.S.ci, newc.p, lv.cf, h->derr + 6, h->stream);
+            // two rounds per read-back of the counters (those of the second round):
+            // once no point is undecided a round changes nothing, and a round
+            // without progress repeats itself, so the outcome is that of checking
+            // after every round
+            for (int round = 0;; round += 2) {
+                for (int r = 0; r < 2; ++r) {
+                    reset_err(h);
+                    launch_pmis_select(n, lv.S.rp, lv.S.ci, ST.rp, ST.ci, lv.cf, o.pmis_seed, newc.p, h->stream);
+                    launch_pmis_update(n, lv.S.rp, lv.S.ci, newc.p, lv.cf, h->derr + 6, h->stream);
+                }
                 read_err(h);
                 if (h->herr[6] == 0) break;
                 if (h->herr[7] == 0 || round > 100000) throw_err(h, MGR_E_INVALID, "PMIS made no progress");
