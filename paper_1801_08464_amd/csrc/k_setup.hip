@@ -665,7 +665,6 @@ __device__ inline int find_col(const int32_t *cols, int len, int key) {
 // (abar_km = a_km when a_km a_kk < 0, else 0); den == 0 lumps a_ik into atil,
 // otherwise num_j += (a_ik abar_kj) / den; w_ij = -((a_ij + num_j) / atil).
 constexpr int kInterpMaxC = 256;  // strong C neighbours per row held in LDS by the wavefront form
-constexpr int kInterpWaves = 4;   // rows (wavefronts) per workgroup of the wavefront form
 
 __global__ void k_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
                               const uint8_t *sflag, const int32_t *cf, const int32_t *cmap, const int32_t *Prp,
@@ -730,14 +729,17 @@ __global__ void k_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, c
     }
 }
 
-// The same interpolation with one wavefront per F row (the thread-per-row form
-// above serialises every distance-two lookup of a row in one lane).  The row's
-// strong C neighbours (ascending, at most kInterpMaxC of them), their a_ij and the
-// running num_j live in LDS.  Strong F neighbours k are taken in ascending order;
-// the lanes load row k together, find each column's place in the C list by binary
-// search, and the sums (atil over the weak entries, den over row k) walk the
-// ballot masks in ascending lane order, so every sum runs in the order above.
-// Rows with more strong C neighbours are left to k_interp_fill.
+// The same interpolation with one group of G lanes per F row (the thread-per-row
+// form above serialises every distance-two lookup of a row in one lane).  The
+// row's strong C neighbours (ascending, at most MAXC of them), their a_ij and
+// the running num_j live in LDS.  Strong F neighbours k are taken in ascending
+// order; the lanes load row k together, find each column's place in the C list
+// by binary search, and the sums (atil over the weak entries, den over row k)
+// walk the group's ballot masks in ascending lane order, chunk after chunk, so
+// every sum runs in the order above whatever G is.  G = 16 serves the rows with
+// at most 32 strong C neighbours (most rows: a wavefront per row would leave
+// most lanes idle), G = 64 those with up to kInterpMaxC; longer rows are left
+// to k_interp_fill.
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -745,35 +747,56 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// acc + the values of the lanes in mask, added one at a time in ascending lane order
-__device__ inline double ordered_add(double acc, unsigned long long mask, double val) {
-    while (mask) {
-        const int l = __builtin_ctzll(mask);
-        acc = acc + __shfl(val, l);
-        mask &= mask - 1;
-    }
-    return acc;
-}
+constexpr int kInterpSmallC = 32;  // strong C neighbours per row of the 16-lane form
 
-__global__ void __launch_bounds__(kInterpWaves * kWave) k_interp_fill_wave(
+template <int G>
+struct InterpGroup {
+    int lane, gbase;
+    unsigned long long gmask;
+    __device__ InterpGroup() {
+        lane = threadIdx.x & (G - 1);
+        gbase = (threadIdx.x & (kWave - 1)) & ~(G - 1);
+        gmask = G == kWave ? ~0ull : ((1ull << G) - 1);
+    }
+    // the group's lanes where pred holds, as a G-bit mask
+    __device__ unsigned long long ballot(bool pred) const { return (__ballot(pred) >> gbase) & gmask; }
+    template <typename T>
+    __device__ T shfl(T val, int l) const {
+        return __shfl(val, gbase + l);
+    }
+    // acc + the values of the lanes in mask, added one at a time in ascending lane order
+    __device__ double ordered_add(double acc, unsigned long long mask, double val) const {
+        while (mask) {
+            const int l = __builtin_ctzll(mask);
+            acc = acc + __shfl(val, gbase + l);
+            mask &= mask - 1;
+        }
+        return acc;
+    }
+};
+
+template <int G, int MAXC, int LO>
+__global__ void __launch_bounds__(256) k_interp_fill_grp(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ v,
     const uint8_t *__restrict__ sflag, const int32_t *__restrict__ cf, const int32_t *__restrict__ cmap,
     const int32_t *__restrict__ Prp, int32_t *__restrict__ Pci, double *__restrict__ Pv) {
-    __shared__ int s_cols[kInterpWaves][kInterpMaxC];
-    __shared__ double s_num[kInterpWaves][kInterpMaxC];
-    __shared__ double s_aij[kInterpWaves][kInterpMaxC];
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int64_t i = (int64_t)blockIdx.x * kInterpWaves + w;
+    constexpr int RPB = 256 / G;  // rows per workgroup
+    __shared__ int s_cols[RPB][MAXC];
+    __shared__ double s_num[RPB][MAXC];
+    __shared__ double s_aij[RPB][MAXC];
+    const InterpGroup<G> grp;
+    const int lane = grp.lane, w = threadIdx.x / G;
+    const int64_t i = (int64_t)blockIdx.x * RPB + w;
     if (i >= n) return;
     const int base = Prp[i], nci = Prp[i + 1] - base;
     if (cf[i] == 1) {
-        if (lane == 0) {
+        if (LO == 0 && lane == 0) {  // C rows: written by the first form only
             Pci[base] = cmap[i];
             Pv[base] = 1.0;
         }
         return;
     }
-    if (nci == 0 || nci > kInterpMaxC) return;
+    if (nci == 0 || nci <= LO || nci > MAXC) return;
     int *cols = s_cols[w];
     double *num = s_num[w], *aij = s_aij[w];
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
@@ -781,13 +804,13 @@ __global__ void __launch_bounds__(kInterpWaves * kWave) k_interp_fill_wave(
     // the strong C neighbours (ascending) and the diagonal
     int nc = 0;
     double aii = 0.0;
-    for (int c0 = a; c0 < b; c0 += kWave) {
+    for (int c0 = a; c0 < b; c0 += G) {
         const int p = c0 + lane;
         const bool ok = p < b;
         const int j = ok ? ci[p] : -1;
         const double vv = ok ? v[p] : 0.0;
         const bool sc = ok && sflag[p] && cf[j] == 1;
-        const unsigned long long m = __ballot(sc);
+        const unsigned long long m = grp.ballot(sc);
         if (sc) {
             const int pos = nc + __popcll(m & below);
             cols[pos] = cmap[j];
@@ -796,53 +819,53 @@ __global__ void __launch_bounds__(kInterpWaves * kWave) k_interp_fill_wave(
             Pci[base + pos] = cmap[j];
         }
         nc += __popcll(m);
-        const unsigned long long md = __ballot(ok && j == i);
-        if (md) aii = __shfl(vv, __builtin_ctzll(md));
+        const unsigned long long md = grp.ballot(ok && j == i);
+        if (md) aii = grp.shfl(vv, __builtin_ctzll(md));
     }
     wave_sync();
     // atil = a_ii + the weak entries, ascending
     double atil = aii;
-    for (int c0 = a; c0 < b; c0 += kWave) {
+    for (int c0 = a; c0 < b; c0 += G) {
         const int p = c0 + lane;
         const bool ok = p < b;
         const bool weak = ok && ci[p] != i && !sflag[p];
-        atil = ordered_add(atil, __ballot(weak), ok ? v[p] : 0.0);
+        atil = grp.ordered_add(atil, grp.ballot(weak), ok ? v[p] : 0.0);
     }
     // the strong F neighbours k, ascending
-    for (int c0 = a; c0 < b; c0 += kWave) {
+    for (int c0 = a; c0 < b; c0 += G) {
         const int p = c0 + lane;
         const bool ok = p < b;
         const int j = ok ? ci[p] : -1;
         const double vv = ok ? v[p] : 0.0;
-        unsigned long long mk = __ballot(ok && j != i && sflag[p] && cf[j] == -1);
+        unsigned long long mk = grp.ballot(ok && j != i && sflag[p] && cf[j] == -1);
         while (mk) {
             const int l = __builtin_ctzll(mk);
             mk &= mk - 1;
-            const int k = __shfl(j, l);
-            const double aik = __shfl(vv, l);
+            const int k = grp.shfl(j, l);
+            const double aik = grp.shfl(vv, l);
             const int ka = rp[k], kb = rp[k + 1];
             double akk = 0.0;
-            for (int d0 = ka; d0 < kb; d0 += kWave) {
+            for (int d0 = ka; d0 < kb; d0 += G) {
                 const int q = d0 + lane;
                 const bool okq = q < kb;
-                const unsigned long long md = __ballot(okq && ci[q] == k);
-                if (md) akk = __shfl(okq ? v[q] : 0.0, __builtin_ctzll(md));
+                const unsigned long long md = grp.ballot(okq && ci[q] == k);
+                if (md) akk = grp.shfl(okq ? v[q] : 0.0, __builtin_ctzll(md));
             }
             double den = 0.0;
-            for (int d0 = ka; d0 < kb; d0 += kWave) {
+            for (int d0 = ka; d0 < kb; d0 += G) {
                 const int q = d0 + lane;
                 const bool okq = q < kb;
                 const int mcol = okq ? ci[q] : 0;
                 const int pos = (okq && cf[mcol] == 1) ? find_col(cols, nc, cmap[mcol]) : -1;
                 const double akm = okq ? v[q] : 0.0;
                 const double abar = (akm * akk < 0.0) ? akm : 0.0;
-                den = ordered_add(den, __ballot(pos >= 0), abar);
+                den = grp.ordered_add(den, grp.ballot(pos >= 0), abar);
             }
             if (den == 0.0) {
                 atil = atil + aik;
                 continue;
             }
-            for (int d0 = ka; d0 < kb; d0 += kWave) {
+            for (int d0 = ka; d0 < kb; d0 += G) {
                 const int q = d0 + lane;
                 const bool okq = q < kb;
                 const int mcol = okq ? ci[q] : 0;
@@ -858,7 +881,7 @@ __global__ void __launch_bounds__(kInterpWaves * kWave) k_interp_fill_wave(
         }
     }
     wave_sync();
-    for (int t = lane; t < nc; t += kWave) {
+    for (int t = lane; t < nc; t += G) {
         const double sum = aij[t] + num[t];
         Pv[base + t] = (atil == 0.0) ? 0.0 : -(sum / atil);
     }
@@ -1100,8 +1123,10 @@ void launch_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const d
                         const int32_t *cf, const int32_t *cmap, const int32_t *Prp, int32_t *Pci, double *Pv,
                         hipStream_t s) {
     if (n <= 0) return;
-    k_interp_fill_wave<<<nblocks(n, kInterpWaves), kInterpWaves * kWave, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp,
-                                                                                  Pci, Pv);
+    k_interp_fill_grp<16, kInterpSmallC, 0><<<nblocks(n, 256 / 16), 256, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp,
+                                                                                 Pci, Pv);
+    k_interp_fill_grp<kWave, kInterpMaxC, kInterpSmallC><<<nblocks(n, 256 / kWave), 256, 0, s>>>(
+        n, rp, ci, v, sflag, cf, cmap, Prp, Pci, Pv);
     k_interp_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp, Pci, Pv);
 }
 void launch_l1(int64_t n, const int32_t *rp, const double *v, double *l1, int *err, hipStream_t s) {
