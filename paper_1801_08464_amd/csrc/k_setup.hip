@@ -1069,6 +1069,7 @@ void launch_spgemm(int pass, int group, int64_t m, const int32_t *Arp, const int
         else spgemm_g<true, G>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err, s);            \
     } while (0)
     switch (group) {
+    case 4: MGR_SPG(4); break;
     case 8: MGR_SPG(8); break;
     case 16: MGR_SPG(16); break;
     case 32: MGR_SPG(32); break;

@@ -248,8 +248,11 @@ int choose_lanes(const DCsr &A) {
     return 32;
 }
 
-// lanes per output row: the smallest group whose 8 chunks hold A's longest row
-int spgemm_group(int maxlen) { return maxlen <= 64 ? 8 : maxlen <= 128 ? 16 : maxlen <= 256 ? 32 : 64; }
+// lanes per output row: the smallest group (4 to 64 lanes) whose 8 chunks hold
+// A's longest row (4 lanes: rows of up to 32 entries, most Galerkin operands)
+int spgemm_group(int maxlen) {
+    return maxlen <= 32 ? 4 : maxlen <= 64 ? 8 : maxlen <= 128 ? 16 : maxlen <= 256 ? 32 : 64;
+}
 
 DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     DCsr C;
