@@ -260,10 +260,10 @@ DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     C.ncols = B.ncols;
     Tmp<int32_t> cnt(h, A.nrows);
     C.rp = scratch ? salloc<int32_t>(h, A.nrows + 1) : dalloc<int32_t>(h, A.nrows + 1);
-    // count with the smallest group first; a row too long for it (the kernel's
-    // error word, read with the scan total) sends the count to the group that
-    // the longest row needs
-    int group = spgemm_group(0);
+    // count with the group that twice the mean row length needs; a row too long
+    // for it (the kernel's error word, read with the scan total) sends the count
+    // to the group that the longest row needs
+    int group = spgemm_group(A.nrows > 0 ? (int)(2 * A.nnz / A.nrows + 1) : 0);
     reset_err(h);
     launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
                   h->stream);
