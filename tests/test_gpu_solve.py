@@ -246,3 +246,18 @@ def test_kernel_timing_counts_and_bytes():
     with pytest.raises(Exception):
         g.kernel_time(3)
     g.close()
+
+
+def test_reused_device_blocks_give_the_same_bits():
+    # a destroyed handle's device blocks are reused by the next handle (with the
+    # old contents in them): the results must not depend on that
+    s = small_system((21, 17, 6), seed=13, sigma=2.0, frac=0.3, region="ball")
+    outs = []
+    for precision in ("fp64", "fp64", "mixed", "mixed"):
+        g = gpu_solver(s, precision=precision, frelax_amg_mask=2)
+        x, info = g.solve(s.b, 1e-10)
+        outs.append((precision, info.iterations, x.cpu().numpy()))
+        g.close()
+    for a, b in ((0, 1), (2, 3)):
+        assert outs[a][1] == outs[b][1]
+        np.testing.assert_array_equal(outs[a][2], outs[b][2])
