@@ -80,10 +80,15 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
     const int64_t re = rb + ROWS < nrows ? rb + ROWS : nrows;
     const int64_t row = rb + tid;
     const int p0 = rp[rb], p1 = rp[re];
+    // the row's output operands: loaded up front in FP32 (the registers are
+    // there), after the passes in FP64 (where they would cost a wave per SIMD)
+    constexpr bool kEarlyRowIn = sizeof(T) == 4;
     int a = 0, b = 0;
+    RowIn<T, MODE> in;
     if (row < re) {
         a = rp[row];
         b = rp[row + 1];
+        if (kEarlyRowIn) in.load(row, x, r, d, y);
     }
     T acc = 0;
     int j[B];
@@ -114,8 +119,7 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
         __syncthreads();
     }
     if (row < re) {
-        RowIn<T, MODE> in;
-        in.load(row, x, r, d, y);
+        if (!kEarlyRowIn) in.load(row, x, r, d, y);
         in.store(row, acc, y, y2);
     }
 }
