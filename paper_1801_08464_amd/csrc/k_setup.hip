@@ -295,6 +295,31 @@ __global__ void k_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, c
     }
 }
 
+// The F columns of A (fmap >= 0) in every row, column numbers kept.  When the
+// error vector vanishes on the C points, the residual r - A e reads only these
+// entries; the skipped products are exact zeros, so the row sums are unchanged.
+__global__ void k_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    int c = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) c += fmap[ci[p]] >= 0;
+    cnt[i] = c;
+}
+
+__global__ void k_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
+                            const int32_t *Frp, int32_t *Fci, double *Fv) {
+    int64_t i = gtid();
+    if (i >= n) return;
+    int q = Frp[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        if (fmap[j] < 0) continue;
+        Fci[q] = j;
+        Fv[q] = v[p];
+        q++;
+    }
+}
+
 // ---------------- SpGEMM: one wavefront per output row ----------------
 // Lane l holds the entries t = l, l+64, ... of row i of A (ascending k) and a
 // cursor into row k of B.  Each step takes the smallest head column j over the
@@ -1045,6 +1070,14 @@ void launch_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const 
 void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
                     const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s) {
     if (nF > 0) k_ff_fill<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, v, fmap, Frp, Fci, Fv);
+}
+void launch_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt,
+                       hipStream_t s) {
+    if (n > 0) k_fcol_count<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, fmap, cnt);
+}
+void launch_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
+                      const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s) {
+    if (n > 0) k_fcol_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, fmap, Frp, Fci, Fv);
 }
 int spgemm_max_row() { return kWave * kSpgChunks; }
 void launch_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx, hipStream_t s) {

@@ -404,6 +404,19 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
         launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
         lv.flanes = choose_lanes(lv.AF);
     }
+    // the F columns of A (all rows) for the residual that precedes the
+    // restriction, at the levels where e is zero on the C points there (no global
+    // relaxation, pre-smoothing cycle)
+    if (lv.nF > 0 && !h->o.cycle_post && !(l == 0 && h->o.global_relax)) {
+        Tmp<int32_t> cnt(h, n);
+        launch_fcol_count(n, A.rp, A.ci, lv.fmap, cnt.p, h->stream);
+        lv.AcF.nrows = lv.AcF.ncols = n;
+        lv.AcF.rp = dalloc<int32_t>(h, n + 1);
+        lv.AcF.nnz = scan(h, cnt.p, lv.AcF.rp, n);
+        lv.AcF.ci = dalloc<int32_t>(h, lv.AcF.nnz);
+        lv.AcF.v = dalloc<double>(h, lv.AcF.nnz);
+        launch_fcol_fill(n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, h->stream);
+    }
     // optional F-relaxation by one AMG V-cycle on A_FF
     if (((h->o.frelax_amg_mask >> l) & 1) && lv.nF > 0) {
         Tmp<int32_t> cnt(h, lv.nF);
@@ -613,6 +626,7 @@ void to_mixed(mgr_handle *h, bool update = false) {
         cast(lv.P.vf, lv.P.v, lv.P.nnz);
         cast(lv.R.vf, lv.R.v, lv.R.nnz);
         if (lv.AF.v) cast(lv.AF.vf, lv.AF.v, lv.AF.nnz);
+        if (lv.AcF.v) cast(lv.AcF.vf, lv.AcF.v, lv.AcF.nnz);
         cast(lv.dinvf, lv.dinv, lv.nF);
         if (lv.ff) amg_to_mixed(h, *lv.ff);
     }
@@ -901,8 +915,10 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
         P_<T>::fill(e, lv.n, s);
         acct(h, S * n);
     }
-    // (3) coarse-grid correction e += P M_c^{-1} R (r - A e)
-    if (l == 0) fine_op<T>(h, 1, e, r, t);
+    // (3) coarse-grid correction e += P M_c^{-1} R (r - A e); without a global
+    // relaxation e is zero on the C points here, so r - A e needs only A's F columns
+    if (lv.AcF.v && !global) csr<T>(h, 1, lv.AcF, P_<T>::v(lv.AcF), e, r, nullptr, t);
+    else if (l == 0) fine_op<T>(h, 1, e, r, t);
     else csr<T>(h, 1, lv.A, Av, e, r, nullptr, t);
     coarse_correction(t);
     csr<T>(h, 2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
@@ -1125,6 +1141,8 @@ void update_mgr_level(mgr_handle *h, int l, DCsr &Anext) {
     ScratchScope scope(h);
     fdiag_inverse(h, l);
     if (lv.AF.v) launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
+    if (lv.AcF.v)
+        launch_fcol_fill(lv.n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, h->stream);
     if (lv.Aff.v) {  // the level relaxes its F points with an AMG cycle on A_FF
         launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, lv.Aff.rp, lv.Aff.ci, lv.Aff.v, h->stream);
         lv.ff = std::make_shared<AmgHier>();

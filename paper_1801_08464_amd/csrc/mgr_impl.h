@@ -67,6 +67,7 @@ struct MgrLevel {
     int32_t *cmap = nullptr;  // level row -> coarse index (-1 on F points)
     bool aff_diag = false;  // A_FF diagonal: the F-relaxation may update in place
     DCsr AF;                // compact copy of the F rows (all columns), row f = level row flist[f]
+    DCsr AcF;               // the F columns of A (all rows, level numbering): r - A e when e_C = 0
     int flanes = 1;         // threads per F row in the F-point residual / relaxation kernels
     DCsr Aff;                     // A_FF (level 0 of ff), kept with the pattern-bound data
     std::shared_ptr<AmgHier> ff;  // AMG V-cycle on A_FF as the F-relaxation (else Jacobi)
@@ -195,6 +196,10 @@ void launch_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const 
                      int32_t *cnt, hipStream_t s);
 void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
                     const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s);
+void launch_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt,
+                       hipStream_t s);
+void launch_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
+                      const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s);
 // SpGEMM C = A B, canonical ascending-k summation.  pass 0 counts into cnt, pass 1 fills.
 // group = lanes per output row (8, 16, 32, 64); rows of A may hold up to group * 8 entries.
 int spgemm_max_row();
