@@ -1,9 +1,13 @@
 // Krylov kernels of restarted GMRES: fused multi-dot and multi-AXPY passes over
-// the Arnoldi basis (classical Gram-Schmidt with a DGKS re-orthogonalisation
-// pass when the norm drops below 1/sqrt(2) of its value before the pass), the
-// Givens update of the Hessenberg column and the small triangular solve.
+// the Arnoldi basis, the Givens update of the Hessenberg column and the small
+// triangular solve.  Restart lengths up to 32 use classical Gram-Schmidt twice
+// with the second pass lagged by one step (two reads of the basis per step);
+// longer ones classical Gram-Schmidt with a DGKS re-orthogonalisation pass when
+// the norm drops below 1/sqrt(2) of its value before the pass.
 // Reductions are two-stage (fixed grid of per-block partials, then one block
 // summing the partials in order), so results do not depend on scheduling.
+#include <stdexcept>
+
 #include "mgr_impl.h"
 
 namespace mgr {
@@ -289,6 +293,217 @@ __global__ void __launch_bounds__(BT) k_norm_fin(int nblk, const double *__restr
     if (threadIdx.x == 0) out[0] = sqrt(s);
 }
 
+
+// ---- Arnoldi with lagged re-orthogonalisation ----
+// Classical Gram-Schmidt applied twice to every basis vector, the second pass of
+// vector j merged with the first pass of the operator image of vector j, so each
+// step reads the basis twice instead of three times.  At step j, columns
+// 0..j-1 hold the final orthonormal v_i and column j holds u_j, the previous
+// step's image after one projection, with norm s_j (u_0 = v_0, s_0 = 1).  The
+// preconditioner and the operator are applied to u_j itself: z_j and w = A z_j
+// carry the scale s_j, which the coefficients absorb.  One pass gives
+// p_i = <V_i, w> (i <= j) and q_i = <V_i, u_j> (i <= j, q_j = <u_j, u_j>); with
+// a = q/s_j (i < j) and beta^2 = q_j/s_j^2 - |a|^2, v_j = (u_j/s_j - V a)/beta,
+// and the projection of w/s_j on v_0..v_j has h_i = p_i/s_j (i < j),
+// h_j = (p_j/s_j^2 - <a, h>)/beta.  The second pass writes v_j over u_j and the
+// projected remainder u_{j+1} into column j+1 with its norm s_{j+1}.  Column
+// j-1 of the Hessenberg matrix, first taken with u_j as its last basis vector,
+// gains s_j a above and s_j beta below the diagonal, and its Givens rotation is
+// rebuilt before column j is rotated.
+
+template <int K>
+__device__ inline void write_partials_k(const double (&acc)[K], double (*sh)[K], double *part) {
+    const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const double v = wave_sum(acc[i]);
+        if (l == 0) sh[wv][i] = v;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < K) {
+        double s = sh[0][t];
+#pragma unroll
+        for (int k = 1; k < BT / kWave; ++k) s = s + sh[k][t];
+        part[(int64_t)blockIdx.x * K + t] = s;
+    }
+}
+
+// part[b*2NV + i] = partial of <V_i, w> (i < NV), part[b*2NV + NV + i] = partial
+// of <V_i, u> with u = V_{NV-1}
+template <int NV>
+__global__ void __launch_bounds__(BT) k_lag_dots(int64_t n2, int64_t ld, const double *__restrict__ V,
+                                                 const double *__restrict__ w, double *__restrict__ part) {
+    __shared__ double sh[BT / kWave][2 * NV];
+    double acc[2 * NV];
+#pragma unroll
+    for (int i = 0; i < 2 * NV; ++i) acc[i] = 0.0;
+    const double2 *w2 = reinterpret_cast<const double2 *>(w);
+    const int64_t stride = (int64_t)gridDim.x * BT;
+    for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < n2; q += stride) {
+        const double2 wq = w2[q];
+        const double2 uq = vec2(V, NV - 1, ld)[q];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double2 vi = (i == NV - 1) ? uq : vec2(V, i, ld)[q];
+            acc[i] = acc[i] + wq.x * vi.x;
+            acc[i] = acc[i] + wq.y * vi.y;
+            acc[NV + i] = acc[NV + i] + uq.x * vi.x;
+            acc[NV + i] = acc[NV + i] + uq.y * vi.y;
+        }
+    }
+    write_partials_k<2 * NV>(acc, sh, part);
+}
+
+// Rotations 0..c-1 (final) applied to the unrotated column c, then rotation c
+// from its diagonal and subdiagonal entries; g(c), g(c+1) from g(c) before it.
+__device__ inline void rotate_column(int c, int m, double *dsc) {
+    for (int i = 0; i <= c; ++i) dsc[Dsc::H(i, c, m)] = dsc[Dsc::Hraw(i, c, m)];
+    const double hn = dsc[Dsc::Hraw(c + 1, c, m)];
+    for (int i = 0; i < c; ++i) {
+        const double a = dsc[Dsc::H(i, c, m)], b = dsc[Dsc::H(i + 1, c, m)];
+        const double cs = dsc[Dsc::cs(i, m)], sn = dsc[Dsc::sn(i, m)];
+        dsc[Dsc::H(i, c, m)] = cs * a + sn * b;
+        dsc[Dsc::H(i + 1, c, m)] = -sn * a + cs * b;
+    }
+    const double a = dsc[Dsc::H(c, c, m)];
+    const double den = sqrt(a * a + hn * hn);
+    double cs = 1.0, sn = 0.0;
+    if (den != 0.0) {
+        cs = a / den;
+        sn = hn / den;
+    }
+    dsc[Dsc::cs(c, m)] = cs;
+    dsc[Dsc::sn(c, m)] = sn;
+    dsc[Dsc::H(c, c, m)] = cs * a + sn * hn;
+    dsc[Dsc::H(c + 1, c, m)] = 0.0;
+    const double g0 = dsc[Dsc::gpre(c, m)];
+    dsc[Dsc::g(c, m)] = cs * g0;
+    dsc[Dsc::g(c + 1, m)] = -sn * g0;
+}
+
+// stage 0 (2(j+1) blocks): block i sums partial i into hcur (p) / h2 (q)
+// stage 1 (one thread): the coefficient algebra of step j
+__global__ void __launch_bounds__(BT) k_lag_coef(int stage, int j, int m, int nblk, const double *__restrict__ part,
+                                                 double *__restrict__ dsc) {
+    const int nv = j + 1;
+    if (stage == 0) {
+        __shared__ double sh[BT / kWave];
+        const int i = blockIdx.x;
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += BT) s += part[(int64_t)b * (2 * nv) + i];
+        s = block_sum(s, sh);
+        if (threadIdx.x == 0) dsc[i < nv ? Dsc::hcur(i, m) : Dsc::h2(i - nv, m)] = s;
+        return;
+    }
+    if (threadIdx.x != 0) return;
+    const double *p = dsc + Dsc::hcur(0, m), *q = dsc + Dsc::h2(0, m);
+    dsc[Dsc::BRK] = 0.0;
+    double beta = 1.0, sj = 1.0;
+    if (j == 0) {
+        dsc[Dsc::sc(0, m)] = 1.0;
+    } else {
+        sj = dsc[Dsc::sc(j, m)];
+        const double is = 1.0 / sj;
+        double aa = 0.0;
+        for (int i = 0; i < j; ++i) {
+            const double a = q[i] * is;
+            dsc[Dsc::ca(i, m)] = a;
+            aa = aa + a * a;
+        }
+        const double b2 = q[j] * is * is - aa;
+        if (!(b2 > 0.0) || !isfinite(b2)) {  // u_j lies in the span of v_0..v_{j-1}
+            dsc[Dsc::BRK] = 1.0;
+            return;
+        }
+        beta = sqrt(b2);
+        for (int i = 0; i < j; ++i) dsc[Dsc::Hraw(i, j - 1, m)] += sj * dsc[Dsc::ca(i, m)];
+        dsc[Dsc::Hraw(j, j - 1, m)] = sj * beta;
+        rotate_column(j - 1, m, dsc);
+    }
+    const double is = 1.0 / sj;
+    double ah = 0.0;
+    for (int i = 0; i < j; ++i) {
+        const double hi = p[i] * is;
+        dsc[Dsc::Hraw(i, j, m)] = hi;
+        dsc[Dsc::ch(i, m)] = hi;
+        ah = ah + dsc[Dsc::ca(i, m)] * hi;
+    }
+    const double hj = (p[j] * is * is - ah) / beta;
+    dsc[Dsc::Hraw(j, j, m)] = hj;
+    dsc[Dsc::ch(j, m)] = hj;
+    for (int i = 0; i < j; ++i) dsc[Dsc::ca(i, m)] /= beta;
+    dsc[Dsc::ALPHA] = is / beta;
+    dsc[Dsc::INVS] = is;
+}
+
+// v_j = alpha u_j - sum_{i<j} ca_i v_i over column j; u_{j+1} = w/s_j -
+// sum_{i<=j} ch_i v_i into column j+1; part[b] = partial of |u_{j+1}|^2
+template <int NV>
+__global__ void __launch_bounds__(BT) k_lag_update(int64_t n2, int64_t ld, const double *__restrict__ V,
+                                                   double *Uj, double *__restrict__ Un,
+                                                   const double *__restrict__ w, const double *__restrict__ dsc,
+                                                   int m, double *__restrict__ part) {
+    if (dsc[Dsc::BRK] != 0.0) return;
+    __shared__ double sh[BT / kWave];
+    double ca[NV > 1 ? NV - 1 : 1], ch[NV];
+#pragma unroll
+    for (int i = 0; i + 1 < NV; ++i) ca[i] = dsc[Dsc::ca(i, m)];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) ch[i] = dsc[Dsc::ch(i, m)];
+    const double alpha = dsc[Dsc::ALPHA], invs = dsc[Dsc::INVS];
+    const double2 *w2 = reinterpret_cast<const double2 *>(w);
+    double2 *u2 = reinterpret_cast<double2 *>(Uj);
+    double2 *n2p = reinterpret_cast<double2 *>(Un);
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * BT;
+    for (int64_t q = (int64_t)blockIdx.x * BT + threadIdx.x; q < n2; q += stride) {
+        const double2 uq = u2[q], wq0 = w2[q];
+        double2 vj = make_double2(uq.x * alpha, uq.y * alpha);
+        double2 wq = make_double2(wq0.x * invs, wq0.y * invs);
+#pragma unroll
+        for (int i = 0; i + 1 < NV; ++i) {
+            const double2 vi = vec2(V, i, ld)[q];
+            vj.x = vj.x - ca[i] * vi.x;
+            vj.y = vj.y - ca[i] * vi.y;
+            wq.x = wq.x - ch[i] * vi.x;
+            wq.y = wq.y - ch[i] * vi.y;
+        }
+        wq.x = wq.x - ch[NV - 1] * vj.x;
+        wq.y = wq.y - ch[NV - 1] * vj.y;
+        u2[q] = vj;
+        n2p[q] = wq;
+        acc = acc + wq.x * wq.x;
+        acc = acc + wq.y * wq.y;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// s_{j+1} = |u_{j+1}|; column j taken with u_{j+1} as its last basis vector
+// (subdiagonal s_{j+1}) and rotated; GABS = |g(j+1)|, HN = s_{j+1}
+__global__ void __launch_bounds__(BT) k_lag_givens(int j, int m, int nblk, const double *__restrict__ part,
+                                                   double *__restrict__ dsc) {
+    if (dsc[Dsc::BRK] != 0.0) return;
+    __shared__ double sh[BT / kWave];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += BT) s += part[b];
+    s = block_sum(s, sh);
+    if (threadIdx.x != 0) return;
+    const double hn = sqrt(s);
+    dsc[Dsc::sc(j + 1, m)] = hn;
+    dsc[Dsc::Hraw(j + 1, j, m)] = hn;
+    dsc[Dsc::gpre(j, m)] = dsc[Dsc::g(j, m)];
+    rotate_column(j, m, dsc);
+    dsc[Dsc::GABS] = fabs(dsc[Dsc::g(j + 1, m)]);
+    dsc[Dsc::HN] = hn;
+}
+
+__global__ void k_lag_yscale(int k, int m, double *dsc) {
+    const int i = threadIdx.x;
+    if (i < k) dsc[Dsc::y(i, m)] /= dsc[Dsc::sc(i, m)];
+}
+
 }  // namespace
 
 static unsigned red_grid(int64_t n) {
@@ -360,6 +575,60 @@ void launch_zaxpy(int64_t n, int64_t ld, int nv, const double *Z, const double *
 }
 #undef MGR_NV_DISPATCH
 #undef MGR_NV_CASE
+
+#define MGR_LAG_CASE(KERNEL, N, ...) \
+    case N: KERNEL<N><<<g, BT, 0, s>>>(__VA_ARGS__); break;
+#define MGR_LAG_DISPATCH(KERNEL, nv, ...)                                                               \
+    do {                                                                                                \
+        switch (nv) {                                                                                   \
+            MGR_LAG_CASE(KERNEL, 1, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 2, __VA_ARGS__)                   \
+            MGR_LAG_CASE(KERNEL, 3, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 4, __VA_ARGS__)                   \
+            MGR_LAG_CASE(KERNEL, 5, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 6, __VA_ARGS__)                   \
+            MGR_LAG_CASE(KERNEL, 7, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 8, __VA_ARGS__)                   \
+            MGR_LAG_CASE(KERNEL, 9, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 10, __VA_ARGS__)                  \
+            MGR_LAG_CASE(KERNEL, 11, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 12, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 13, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 14, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 15, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 16, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 17, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 18, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 19, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 20, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 21, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 22, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 23, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 24, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 25, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 26, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 27, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 28, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 29, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 30, __VA_ARGS__)                 \
+            MGR_LAG_CASE(KERNEL, 31, __VA_ARGS__) MGR_LAG_CASE(KERNEL, 32, __VA_ARGS__)                 \
+        default: throw std::runtime_error("lagged Arnoldi: basis wider than 32 vectors");               \
+        }                                                                                               \
+    } while (0)
+
+void launch_lag_dots(int64_t n, int64_t ld, int nv, const double *V, const double *w, double *part, hipStream_t s) {
+    const int64_t n2 = (n + 1) / 2;
+    const unsigned g = red_grid(n);
+    MGR_LAG_DISPATCH(k_lag_dots, nv, n2, ld, V, w, part);
+}
+
+void launch_lag_coef(int j, int m, int nblk, const double *part, double *dsc, hipStream_t s) {
+    k_lag_coef<<<2 * (j + 1), BT, 0, s>>>(0, j, m, nblk, part, dsc);
+    k_lag_coef<<<1, 64, 0, s>>>(1, j, m, nblk, part, dsc);
+}
+
+void launch_lag_update(int64_t n, int64_t ld, int nv, double *V, const double *w, const double *dsc, int m,
+                       double *part, hipStream_t s) {
+    const int64_t n2 = (n + 1) / 2;
+    const unsigned g = red_grid(n);
+    double *Uj = V + (int64_t)(nv - 1) * ld, *Un = V + (int64_t)nv * ld;
+    MGR_LAG_DISPATCH(k_lag_update, nv, n2, ld, V, Uj, Un, w, dsc, m, part);
+}
+#undef MGR_LAG_DISPATCH
+#undef MGR_LAG_CASE
+
+void launch_lag_givens(int j, int m, int nblk, const double *part, double *dsc, hipStream_t s) {
+    k_lag_givens<<<1, BT, 0, s>>>(j, m, nblk, part, dsc);
+}
+
+void launch_lag_yscale(int k, int m, double *dsc, hipStream_t s) {
+    if (k > 0) k_lag_yscale<<<1, 64, 0, s>>>(k, m, dsc);
+}
 
 void launch_norm_part(int64_t n, const double *a, double *part, hipStream_t s) {
     k_norm_part<<<red_grid(n), BT, 0, s>>>(n, a, part);

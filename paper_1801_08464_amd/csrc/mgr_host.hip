@@ -960,6 +960,7 @@ int gmres(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) 
     double *dsc = h->dsc;
     const int nblk = red_blocks(n);
     int *guard = h->derr + 7;
+    const bool lagged = m <= kFusedMaxV;
     if (ld > n) launch_fill_f64(h->w + n, 0.0, ld - n, s);  // a breakdown may have left NaN there
     int its = 0;
     double rel = 0.0;
@@ -1003,19 +1004,34 @@ int gmres(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) 
             double *zj = h->Z + (int64_t)j * ld;
             apply_prec(h, vj, zj);
             fine_op<double>(h, 0, zj, nullptr, h->w);
-            // classical Gram-Schmidt; the DGKS second projection runs only when
-            // the first one cancelled more than half of ||w||^2 (guard on device)
-            launch_mdot(n, ld, j + 1, h->V, h->w, h->part, s);
-            launch_arnoldi_fin(0, j, m, nblk, h->part, dsc, guard, s);
-            launch_maxpy_dot(n, ld, j + 1, h->V, dsc + Dsc::hcur(0, m), h->w, h->part, s);
-            launch_arnoldi_fin(1, j, m, nblk, h->part, dsc, guard, s);
-            launch_maxpy_norm(n, ld, j + 1, h->V, dsc + Dsc::h2(0, m), h->w, h->part, guard, s);
-            launch_arnoldi_fin(3, j, m, nblk, h->part, dsc, guard, s);
-            launch_givens(j, m, dsc, s);
-            HIPCHK(hipMemcpyAsync(h->hsc, dsc + Dsc::GABS, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            if (lagged) {
+                // classical Gram-Schmidt twice, the second pass of column j
+                // merged with the first pass of w (two reads of the basis)
+                launch_lag_dots(n, ld, j + 1, h->V, h->w, h->part, s);
+                launch_lag_coef(j, m, nblk, h->part, dsc, s);
+                launch_lag_update(n, ld, j + 1, h->V, h->w, dsc, m, h->part, s);
+                launch_lag_givens(j, m, nblk, h->part, dsc, s);
+            } else {
+                // classical Gram-Schmidt; the DGKS second projection runs only when
+                // the first one cancelled more than half of ||w||^2 (guard on device)
+                launch_mdot(n, ld, j + 1, h->V, h->w, h->part, s);
+                launch_arnoldi_fin(0, j, m, nblk, h->part, dsc, guard, s);
+                launch_maxpy_dot(n, ld, j + 1, h->V, dsc + Dsc::hcur(0, m), h->w, h->part, s);
+                launch_arnoldi_fin(1, j, m, nblk, h->part, dsc, guard, s);
+                launch_maxpy_norm(n, ld, j + 1, h->V, dsc + Dsc::h2(0, m), h->w, h->part, guard, s);
+                launch_arnoldi_fin(3, j, m, nblk, h->part, dsc, guard, s);
+                launch_givens(j, m, dsc, s);
+            }
+            HIPCHK(hipMemcpyAsync(h->hsc, dsc + Dsc::GABS, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
             sync(h);
             const double gabs = h->hsc[0], hn = h->hsc[1];
             its++;
+            if (lagged && h->hsc[2] != 0.0) {
+                // the second pass found u_j inside the span of v_0..v_{j-1}: the
+                // Krylov space was exhausted at step j-1, which ends the cycle
+                k = j;
+                break;
+            }
             k = j + 1;
             if (st && st->res_history && st->res_history_len < st->res_history_cap)
                 st->res_history[st->res_history_len++] = gabs / bnorm;
@@ -1024,13 +1040,14 @@ int gmres(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *st) 
                 break;
             }
             if (gabs <= tol * bnorm || hn == 0.0 || its >= h->o.max_iter) break;
-            launch_scale_dev(n, h->w, dsc + Dsc::HN, 1, h->V + (int64_t)(j + 1) * ld, s);
+            if (!lagged) launch_scale_dev(n, h->w, dsc + Dsc::HN, 1, h->V + (int64_t)(j + 1) * ld, s);
         }
         if (broke) {
             status = MGR_E_BREAKDOWN;
             break;
         }
         launch_trisolve(k, m, dsc, s);
+        if (lagged) launch_lag_yscale(k, m, dsc, s);
         launch_zaxpy(n, ld, k, h->Z, dsc + Dsc::y(0, m), x, s);
     }
     sync(h);
@@ -1299,7 +1316,7 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
         h->res = dalloc<double>(h, n);
         h->dsc = dalloc<double>(h, Dsc::size(m));
         launch_fill_f64(h->dsc, 0.0, Dsc::size(m), h->stream);
-        h->part = dalloc<double>(h, (int64_t)kRedBlocks * 66);
+        h->part = dalloc<double>(h, (int64_t)kRedBlocks * 130);
         arena_release(h, h->scratch);
         sync(h);
         h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -310,6 +310,16 @@ void launch_arnoldi_fin(int stage, int j, int m, int nblk, const double *part, d
                         hipStream_t s);
 void launch_givens(int j, int m, double *dsc, hipStream_t s);
 void launch_trisolve(int k, int m, double *dsc, hipStream_t s);
+// Arnoldi step j with lagged re-orthogonalisation (restart length <= kFusedMaxV):
+// dots of w and of column j with columns 0..j, the coefficient algebra, the
+// update writing v_j and u_{j+1}, and the Givens step with the norm of u_{j+1}
+void launch_lag_dots(int64_t n, int64_t ld, int nv, const double *V, const double *w, double *part, hipStream_t s);
+void launch_lag_coef(int j, int m, int nblk, const double *part, double *dsc, hipStream_t s);
+void launch_lag_update(int64_t n, int64_t ld, int nv, double *V, const double *w, const double *dsc, int m,
+                       double *part, hipStream_t s);
+void launch_lag_givens(int j, int m, int nblk, const double *part, double *dsc, hipStream_t s);
+// y_i /= s_i (the preconditioned vectors of the lagged form carry the scale s_i)
+void launch_lag_yscale(int k, int m, double *dsc, hipStream_t s);
 void launch_norm_fin(int nblk, const double *part, double *out, hipStream_t s);
 
 // layout of the device scalar block dsc (doubles)
@@ -321,9 +331,18 @@ struct Dsc {
     __host__ __device__ static int y(int i, int m) { return 64 + (m + 1) * m + (m + 1) + 2 * m + i; }
     __host__ __device__ static int hcur(int i, int m) { return 64 + (m + 1) * m + (m + 1) + 3 * m + i; }
     __host__ __device__ static int h2(int i, int m) { return 64 + (m + 1) * m + (m + 1) + 4 * m + i; }
-    __host__ __device__ static int size(int m) { return 64 + (m + 1) * m + (m + 1) + 5 * m + 1 + 8; }
-    // scalar slots
-    enum { BNORM = 0, WN0 = 1, WN = 2, GABS = 3, HN = 4, INVH = 5, BETA = 6, RNORM = 7 };
+    // lagged re-orthogonalisation: the Hessenberg columns before rotation, the
+    // second-pass and projection coefficients of the current step, the norms s_i
+    // of the vectors the preconditioner was applied to, g before each rotation
+    __host__ __device__ static int lag(int m) { return 64 + (m + 1) * m + (m + 1) + 5 * m; }
+    __host__ __device__ static int Hraw(int i, int j, int m) { return lag(m) + i * m + j; }
+    __host__ __device__ static int ca(int i, int m) { return lag(m) + (m + 1) * m + i; }
+    __host__ __device__ static int ch(int i, int m) { return lag(m) + (m + 1) * m + m + i; }
+    __host__ __device__ static int sc(int i, int m) { return lag(m) + (m + 1) * m + 2 * m + i; }
+    __host__ __device__ static int gpre(int i, int m) { return lag(m) + (m + 1) * m + 3 * m + 1 + i; }
+    __host__ __device__ static int size(int m) { return lag(m) + (m + 1) * m + 4 * m + 2 + 8; }
+    // scalar slots (BRK: the lagged second pass found the Krylov space exhausted)
+    enum { BNORM = 0, WN0 = 1, WN = 2, GABS = 3, HN = 4, BRK = 5, BETA = 6, RNORM = 7, ALPHA = 8, INVS = 9 };
 };
 
 }  // namespace mgr
