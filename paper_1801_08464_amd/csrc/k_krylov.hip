@@ -355,31 +355,54 @@ __global__ void __launch_bounds__(BT) k_lag_dots(int64_t n2, int64_t ld, const d
     write_partials_k<2 * NV>(acc, sh, part);
 }
 
-// Rotations 0..c-1 (final) applied to the unrotated column c, then rotation c
-// from its diagonal and subdiagonal entries; g(c), g(c+1) from g(c) before it.
-__device__ inline void rotate_column(int c, int m, double *dsc) {
-    for (int i = 0; i <= c; ++i) dsc[Dsc::H(i, c, m)] = dsc[Dsc::Hraw(i, c, m)];
-    const double hn = dsc[Dsc::Hraw(c + 1, c, m)];
+// Rotations 0..c-1 (final) applied to col[0..c] (the unrotated column c, its
+// subdiagonal in col[c+1]), then rotation c from the diagonal and subdiagonal;
+// g(c), g(c+1) from g0 = g(c) before it.  One thread, operands in LDS.
+__device__ inline void rotate_lds(int c, double *col, const double *cs, const double *sn, double g0, double *out) {
+    const double hn = col[c + 1];
     for (int i = 0; i < c; ++i) {
-        const double a = dsc[Dsc::H(i, c, m)], b = dsc[Dsc::H(i + 1, c, m)];
-        const double cs = dsc[Dsc::cs(i, m)], sn = dsc[Dsc::sn(i, m)];
-        dsc[Dsc::H(i, c, m)] = cs * a + sn * b;
-        dsc[Dsc::H(i + 1, c, m)] = -sn * a + cs * b;
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
     }
-    const double a = dsc[Dsc::H(c, c, m)];
+    const double a = col[c];
     const double den = sqrt(a * a + hn * hn);
-    double cs = 1.0, sn = 0.0;
+    double csc = 1.0, snc = 0.0;
     if (den != 0.0) {
-        cs = a / den;
-        sn = hn / den;
+        csc = a / den;
+        snc = hn / den;
     }
-    dsc[Dsc::cs(c, m)] = cs;
-    dsc[Dsc::sn(c, m)] = sn;
-    dsc[Dsc::H(c, c, m)] = cs * a + sn * hn;
-    dsc[Dsc::H(c + 1, c, m)] = 0.0;
-    const double g0 = dsc[Dsc::gpre(c, m)];
-    dsc[Dsc::g(c, m)] = cs * g0;
-    dsc[Dsc::g(c + 1, m)] = -sn * g0;
+    col[c] = csc * a + snc * hn;
+    col[c + 1] = 0.0;
+    out[0] = csc;
+    out[1] = snc;
+    out[2] = csc * g0;
+    out[3] = -snc * g0;
+}
+
+// Stage the unrotated column c (rows 0..c+1) and rotations 0..c-1 in LDS
+// (threads in parallel), rotate it (thread 0), write the rotated column, the
+// rotation and g(c), g(c+1) back (threads in parallel).  Every thread of the
+// block calls it; `raw` already holds column c when `have_raw`.
+__device__ inline void rotate_column(int c, int m, double *dsc, double *raw, bool have_raw, double *cs, double *sn,
+                                     double *out) {
+    const int t = threadIdx.x;
+    if (!have_raw)
+        for (int i = t; i <= c + 1; i += blockDim.x) raw[i] = dsc[Dsc::Hraw(i, c, m)];
+    for (int i = t; i < c; i += blockDim.x) {
+        cs[i] = dsc[Dsc::cs(i, m)];
+        sn[i] = dsc[Dsc::sn(i, m)];
+    }
+    __syncthreads();
+    if (t == 0) rotate_lds(c, raw, cs, sn, dsc[Dsc::gpre(c, m)], out);
+    __syncthreads();
+    for (int i = t; i <= c + 1; i += blockDim.x) dsc[Dsc::H(i, c, m)] = raw[i];
+    if (t == 0) {
+        dsc[Dsc::cs(c, m)] = out[0];
+        dsc[Dsc::sn(c, m)] = out[1];
+        dsc[Dsc::g(c, m)] = out[2];
+        dsc[Dsc::g(c + 1, m)] = out[3];
+    }
 }
 
 // stage 0 (2(j+1) blocks): block i sums partial i into hcur (p) / h2 (q)
@@ -396,45 +419,72 @@ __global__ void __launch_bounds__(BT) k_lag_coef(int stage, int j, int m, int nb
         if (threadIdx.x == 0) dsc[i < nv ? Dsc::hcur(i, m) : Dsc::h2(i - nv, m)] = s;
         return;
     }
-    if (threadIdx.x != 0) return;
-    const double *p = dsc + Dsc::hcur(0, m), *q = dsc + Dsc::h2(0, m);
-    dsc[Dsc::BRK] = 0.0;
-    double beta = 1.0, sj = 1.0;
-    if (j == 0) {
-        dsc[Dsc::sc(0, m)] = 1.0;
-    } else {
-        sj = dsc[Dsc::sc(j, m)];
+    // stage 1: operands staged in LDS by all threads, the algebra on thread 0
+    __shared__ double sp[kFusedMaxV], sq[kFusedMaxV], sa[kFusedMaxV], sh[kFusedMaxV];
+    __shared__ double raw[kFusedMaxV + 2], cs[kFusedMaxV], sn[kFusedMaxV], out[4];
+    __shared__ double scal[4];  // beta, s_j, broke
+    const int t = threadIdx.x;
+    for (int i = t; i < nv; i += blockDim.x) {
+        sp[i] = dsc[Dsc::hcur(i, m)];
+        sq[i] = dsc[Dsc::h2(i, m)];
+    }
+    if (j >= 1)
+        for (int i = t; i <= j; i += blockDim.x) raw[i] = dsc[Dsc::Hraw(i, j - 1, m)];
+    __syncthreads();
+    if (t == 0) {
+        double beta = 1.0, sj = 1.0, broke = 0.0;
+        if (j >= 1) {
+            sj = dsc[Dsc::sc(j, m)];
+            const double is = 1.0 / sj;
+            double aa = 0.0;
+            for (int i = 0; i < j; ++i) {
+                sa[i] = sq[i] * is;
+                aa = aa + sa[i] * sa[i];
+            }
+            const double b2 = sq[j] * is * is - aa;
+            if (!(b2 > 0.0) || !isfinite(b2)) {  // u_j lies in the span of v_0..v_{j-1}
+                broke = 1.0;
+            } else {
+                beta = sqrt(b2);
+                // column j-1 was taken with u_j as its last basis vector
+                for (int i = 0; i < j; ++i) raw[i] += sj * sa[i];
+                raw[j] = sj * beta;
+            }
+        }
+        scal[0] = beta;
+        scal[1] = sj;
+        scal[2] = broke;
+    }
+    __syncthreads();
+    const double beta = scal[0], sj = scal[1];
+    if (scal[2] != 0.0) {
+        if (t == 0) dsc[Dsc::BRK] = 1.0;
+        return;
+    }
+    if (j >= 1) {
+        for (int i = t; i <= j; i += blockDim.x) dsc[Dsc::Hraw(i, j - 1, m)] = raw[i];
+        rotate_column(j - 1, m, dsc, raw, true, cs, sn, out);
+    }
+    if (t == 0) {
         const double is = 1.0 / sj;
-        double aa = 0.0;
+        double ah = 0.0;
         for (int i = 0; i < j; ++i) {
-            const double a = q[i] * is;
-            dsc[Dsc::ca(i, m)] = a;
-            aa = aa + a * a;
+            sh[i] = sp[i] * is;
+            ah = ah + sa[i] * sh[i];
         }
-        const double b2 = q[j] * is * is - aa;
-        if (!(b2 > 0.0) || !isfinite(b2)) {  // u_j lies in the span of v_0..v_{j-1}
-            dsc[Dsc::BRK] = 1.0;
-            return;
-        }
-        beta = sqrt(b2);
-        for (int i = 0; i < j; ++i) dsc[Dsc::Hraw(i, j - 1, m)] += sj * dsc[Dsc::ca(i, m)];
-        dsc[Dsc::Hraw(j, j - 1, m)] = sj * beta;
-        rotate_column(j - 1, m, dsc);
+        sh[j] = (sp[j] * is * is - ah) / beta;
+        for (int i = 0; i < j; ++i) sa[i] = sa[i] / beta;
+        dsc[Dsc::ALPHA] = is / beta;
+        dsc[Dsc::INVS] = is;
+        dsc[Dsc::BRK] = 0.0;
+        if (j == 0) dsc[Dsc::sc(0, m)] = 1.0;
     }
-    const double is = 1.0 / sj;
-    double ah = 0.0;
-    for (int i = 0; i < j; ++i) {
-        const double hi = p[i] * is;
-        dsc[Dsc::Hraw(i, j, m)] = hi;
-        dsc[Dsc::ch(i, m)] = hi;
-        ah = ah + dsc[Dsc::ca(i, m)] * hi;
+    __syncthreads();
+    for (int i = t; i <= j; i += blockDim.x) {
+        dsc[Dsc::Hraw(i, j, m)] = sh[i];
+        dsc[Dsc::ch(i, m)] = sh[i];
+        if (i < j) dsc[Dsc::ca(i, m)] = sa[i];
     }
-    const double hj = (p[j] * is * is - ah) / beta;
-    dsc[Dsc::Hraw(j, j, m)] = hj;
-    dsc[Dsc::ch(j, m)] = hj;
-    for (int i = 0; i < j; ++i) dsc[Dsc::ca(i, m)] /= beta;
-    dsc[Dsc::ALPHA] = is / beta;
-    dsc[Dsc::INVS] = is;
 }
 
 // v_j = alpha u_j - sum_{i<j} ca_i v_i over column j; u_{j+1} = w/s_j -
@@ -489,14 +539,23 @@ __global__ void __launch_bounds__(BT) k_lag_givens(int j, int m, int nblk, const
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += BT) s += part[b];
     s = block_sum(s, sh);
-    if (threadIdx.x != 0) return;
-    const double hn = sqrt(s);
-    dsc[Dsc::sc(j + 1, m)] = hn;
-    dsc[Dsc::Hraw(j + 1, j, m)] = hn;
-    dsc[Dsc::gpre(j, m)] = dsc[Dsc::g(j, m)];
-    rotate_column(j, m, dsc);
-    dsc[Dsc::GABS] = fabs(dsc[Dsc::g(j + 1, m)]);
-    dsc[Dsc::HN] = hn;
+    __shared__ double raw[kFusedMaxV + 2], cs[kFusedMaxV], sn[kFusedMaxV], out[4], hn_s;
+    const int t = threadIdx.x;
+    for (int i = t; i <= j; i += BT) raw[i] = dsc[Dsc::Hraw(i, j, m)];
+    if (t == 0) {
+        const double hn = sqrt(s);
+        hn_s = hn;
+        raw[j + 1] = hn;
+        dsc[Dsc::sc(j + 1, m)] = hn;
+        dsc[Dsc::Hraw(j + 1, j, m)] = hn;
+        dsc[Dsc::gpre(j, m)] = dsc[Dsc::g(j, m)];
+    }
+    __syncthreads();
+    rotate_column(j, m, dsc, raw, true, cs, sn, out);
+    if (t == 0) {
+        dsc[Dsc::GABS] = fabs(out[3]);
+        dsc[Dsc::HN] = hn_s;
+    }
 }
 
 __global__ void k_lag_yscale(int k, int m, double *dsc) {
