@@ -151,6 +151,24 @@ def test_tiny_systems(orc):
         g.close()
 
 
+@pytest.mark.parametrize("opts", [dict(), dict(restart=64), dict(restart=2), dict(precision="mixed")])
+def test_exhausted_krylov_space_with_zero_tolerance(opts):
+    # one cell (n = 3) and tol = 0: the Krylov space is exhausted after at most
+    # three steps and the iteration continues on rounding noise until max_iter.
+    # The lagged re-orthogonalisation (restart <= 32) detects a vector inside the
+    # span of the basis and ends the cycle; every path must stay finite and keep
+    # the exact solution.
+    s = small_system((1, 1), seed=1, frac=0.5)
+    g = gpu_solver(s, max_iter=12, **opts)
+    x, info = g.solve(s.b, 0.0)
+    xv = x.cpu().numpy()
+    assert info.status in (0, 1) and info.iterations <= 12
+    assert np.all(np.isfinite(xv)) and np.isfinite(info.rel_residual)
+    np.testing.assert_allclose(xv, s.x_true, rtol=1e-9, atol=1e-9)
+    assert info.rel_residual <= 1e-12
+    g.close()
+
+
 def test_zero_rhs_and_initial_guess():
     s = small_system()
     g = gpu_solver(s, use_x0=1)
