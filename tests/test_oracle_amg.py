@@ -217,3 +217,49 @@ def test_amg_gmres_iterations_grow_slowly_with_mesh(orc):
     # (De Sterck, Yang, Heys 2006); growth stays logarithmic in the mesh size.
     assert its == sorted(its)
     assert max(np.diff(its)) <= 6 and its[-1] <= 32, its
+
+
+def _pmis_brute_force(S, lam, h):
+    """PMIS written out from its definition with Python sets (tiny graphs only):
+    points with lambda = 0 start as F; every round, on the states at its start,
+    each undecided point whose key (lambda, hash, index) exceeds the keys of all
+    undecided points it is strongly connected to (either direction) becomes C,
+    then each undecided point that strongly depends on a C point becomes F."""
+    n = S.shape[0]
+    dep = [set(S.indices[S.indptr[i]:S.indptr[i + 1]].tolist()) for i in range(n)]
+    nbr = [set(d) for d in dep]
+    for i in range(n):
+        for j in dep[i]:
+            nbr[j].add(i)
+    key = [(int(lam[i]), int(h[i]), i) for i in range(n)]
+    state = [0 if lam[i] > 0 else -1 for i in range(n)]
+    while 0 in state:
+        und = [i for i in range(n) if state[i] == 0]
+        new_c = [i for i in und if all(state[j] != 0 or key[i] > key[j] for j in nbr[i])]
+        assert new_c, "a round must select at least the largest undecided key"
+        for i in new_c:
+            state[i] = 1
+        for i in und:
+            if state[i] == 0 and any(state[j] == 1 for j in dep[i]):
+                state[i] = -1
+    return np.array(state)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+def test_pmis_equals_brute_force(orc, seed):
+    # random strength graphs of up to 200 points, some directed, some symmetric,
+    # with isolated points and points nobody depends on
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(20, 200))
+    M = sp.random(n, n, density=float(rng.uniform(0.01, 0.08)), random_state=rng, format="csr")
+    if seed % 2:
+        M = M + M.T
+    M = -abs(M) + sp.diags(np.full(n, 50.0))
+    M = sp.csr_matrix(M)
+    M.sort_indices()
+    A = orc.from_scipy(M)
+    S = orc.strength(A, 0.25)
+    pmis_seed = int(rng.integers(0, 2**63))
+    cf = orc.pmis(S, pmis_seed)
+    lam, h = _keys(orc, S, pmis_seed)
+    np.testing.assert_array_equal(cf, _pmis_brute_force(S, lam, h))
