@@ -921,7 +921,14 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
     else if (l == 0) fine_op<T>(h, 1, e, r, t);
     else csr<T>(h, 1, lv.A, Av, e, r, nullptr, t);
     coarse_correction(t);
-    csr<T>(h, 2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
+    if (lv.P.nnz == lv.nC) {
+        // W_p = 0 (every F row of P empty, the C rows the identity): the
+        // prolongation is e_C += e_c
+        launch_scatter_add<T>(lv.nC, lv.clist, ec, e, s);
+        acct(h, 4.0 * (double)lv.nC + 3.0 * S * (double)lv.nC);
+    } else {
+        csr<T>(h, 2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
+    }
 }
 
 void apply_prec(mgr_handle *h, const double *v, double *z) {
