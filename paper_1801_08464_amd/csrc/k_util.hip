@@ -89,8 +89,16 @@ __global__ void __launch_bounds__(kScanBT) k_scan_final(const int32_t *in, int32
 
 __global__ void k_scan_empty(int32_t *out) { out[0] = 0; }
 
+__global__ void k_iota(int32_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
 }  // namespace
 
+void launch_iota(int32_t *p, int64_t n, hipStream_t s) {
+    if (n > 0) k_iota<<<nblocks(n, 256), 256, 0, s>>>(p, n);
+}
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
     if (n > 0) k_fill<int32_t><<<nblocks(n, 256), 256, 0, s>>>(p, v, n);
 }

@@ -1290,12 +1290,7 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
         int32_t *lab = dalloc<int32_t>(h, n);
         int32_t *glob = dalloc<int32_t>(h, n);
         HIPCHK(hipMemcpyAsync(lab, labels, n * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
-        {
-            std::vector<int32_t> iota(n);
-            for (int64_t i = 0; i < n; ++i) iota[i] = (int32_t)i;
-            HIPCHK(hipMemcpyAsync(glob, iota.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-            sync(h);
-        }
+        launch_iota(glob, n, h->stream);
         h->lev.resize(h->L);
         for (int l = 0; l < h->L; ++l) {
             h->lev[l].A = Acur;

@@ -155,6 +155,7 @@ inline int alloc_n(mgr_handle *h, T **p, int64_t n) {
 inline unsigned nblocks(int64_t n, int bt) { return (unsigned)((n + bt - 1) / bt); }
 
 // ---- utility kernels (k_util.hip) ----
+void launch_iota(int32_t *p, int64_t n, hipStream_t s);  // p[i] = i
 void launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
 void launch_fill_f32(float *p, float v, int64_t n, hipStream_t s);
