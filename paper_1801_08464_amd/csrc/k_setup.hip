@@ -30,12 +30,12 @@ __global__ void k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int3
     int a = rp[i], b = rp[i + 1];
     bool bad = a < 0 || b < a || (int64_t)b > nnz;
     if (!bad) {
+        // no early exit: the column loads of a row do not wait for each other
+        int prev = -1;
         for (int p = a; p < b; ++p) {
-            int c = ci[p];
-            if (c < 0 || (int64_t)c >= n || (p > a && c <= ci[p - 1])) {
-                bad = true;
-                break;
-            }
+            const int c = ci[p];
+            bad = bad || c <= prev || (int64_t)c >= n;  // c <= prev also catches c < 0
+            prev = c;
         }
     }
     if (bad) atomicOr(&err[0], 1);
