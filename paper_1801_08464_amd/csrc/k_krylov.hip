@@ -69,6 +69,14 @@ __device__ inline void write_partials(const double (&acc)[NV + 1], int nv, doubl
     }
 }
 
+// Basis vectors read once per pass with non-temporal loads: the 1.6 GB basis
+// does not fit the caches, and streaming it past them keeps w, u_j and the
+// next step's vectors cached.
+typedef double ntd2 __attribute__((ext_vector_type(2)));
+__device__ inline double2 ldnt(const double *base, int i, int64_t ld, int64_t q) {
+    const ntd2 v = __builtin_nontemporal_load(reinterpret_cast<const ntd2 *>(base + (int64_t)i * ld) + q);
+    return make_double2(v.x, v.y);
+}
 __device__ inline const double2 *vec2(const double *base, int i, int64_t ld) {
     return reinterpret_cast<const double2 *>(base + (int64_t)i * ld);
 }
@@ -345,7 +353,7 @@ __global__ void __launch_bounds__(BT) k_lag_dots(int64_t n2, int64_t ld, const d
         const double2 uq = vec2(V, NV - 1, ld)[q];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const double2 vi = (i == NV - 1) ? uq : vec2(V, i, ld)[q];
+            const double2 vi = (i == NV - 1) ? uq : ldnt(V, i, ld, q);
             acc[i] = acc[i] + wq.x * vi.x;
             acc[i] = acc[i] + wq.y * vi.y;
             acc[NV + i] = acc[NV + i] + uq.x * vi.x;
@@ -513,7 +521,7 @@ __global__ void __launch_bounds__(BT) k_lag_update(int64_t n2, int64_t ld, const
         double2 wq = make_double2(wq0.x * invs, wq0.y * invs);
 #pragma unroll
         for (int i = 0; i + 1 < NV; ++i) {
-            const double2 vi = vec2(V, i, ld)[q];
+            const double2 vi = ldnt(V, i, ld, q);
             vj.x = vj.x - ca[i] * vi.x;
             vj.y = vj.y - ca[i] * vi.y;
             wq.x = wq.x - ch[i] * vi.x;
