@@ -263,3 +263,101 @@ def test_pmis_equals_brute_force(orc, seed):
     cf = orc.pmis(S, pmis_seed)
     lam, h = _keys(orc, S, pmis_seed)
     np.testing.assert_array_equal(cf, _pmis_brute_force(S, lam, h))
+
+
+def _interp_rows(orc, D, strong, cf):
+    """Classical interpolation of a small dense matrix with a given strength
+    pattern and C/F split; returns P as a dense array."""
+    A = orc.from_scipy(sp.csr_matrix(D))
+    n = D.shape[0]
+    S = orc.as_csr(np.concatenate([[0], np.cumsum([len(s) for s in strong])]),
+                   np.array([j for s in strong for j in s], dtype=np.int32), None, (n, n))
+    P = orc.interp(A, S, np.asarray(cf, dtype=np.int32))
+    return orc.to_scipy(P).toarray()
+
+
+def test_interp_sign_filter_positive_diagonal_neighbour(orc):
+    # F point 0 with strong C neighbours 1, 2, strong F neighbour 3 and a weak
+    # coupling to 4.  Row 3 has a_33 = 4 > 0: its coupling a_31 = -1 has the
+    # opposite sign (kept in the distance-two sum), a_32 = +1 the same sign
+    # (dropped).  Hand computation:
+    #   atil = a_00 + a_04 = 4 - 0.2 = 3.8
+    #   den  = abar_31 + abar_32 = -1 + 0 = -1
+    #   num_1 = a_03 abar_31 / den = (-1)(-1)/(-1) = -1,  num_2 = 0
+    #   w_01 = -(a_01 + num_1) / atil = 2 / 3.8,  w_02 = -(a_02) / atil = 1 / 3.8
+    # (without the filter den = 0 and a_03 would be lumped into atil: 0.5 / 0.5)
+    D = np.array([[4.0, -1.0, -1.0, -1.0, -0.2],
+                  [-1.0, 4.0, 0.0, -1.0, 0.0],
+                  [-1.0, 0.0, 4.0, 1.0, 0.0],
+                  [-1.0, -1.0, 1.0, 4.0, 0.0],
+                  [-0.2, 0.0, 0.0, 0.0, 4.0]])
+    strong = [[1, 2, 3], [0, 3], [0], [0, 1], []]
+    P = _interp_rows(orc, D, strong, [-1, 1, 1, -1, 1])
+    assert P[0, 0] == 2.0 / 3.8 and P[0, 1] == 1.0 / 3.8 and P[0, 2] == 0.0
+    # C rows are unit rows onto their coarse index
+    np.testing.assert_array_equal(P[[1, 2, 4]], np.eye(3))
+
+
+def test_interp_sign_filter_negative_diagonal_neighbour(orc):
+    # as above, but row 3 has a negative diagonal a_33 = -4: now a_31 = +1 has
+    # the opposite sign (kept) and a_32 = -1 the same sign (dropped).
+    #   atil = 4, den = 1, num_1 = a_03 * 1 / 1 = -2, num_2 = 0
+    #   w_01 = -(-1 - 2) / 4 = 3/4,  w_02 = -(-1) / 4 = 1/4
+    # A filter on the sign of a_km alone (a_km < 0) would keep a_32 instead and
+    # give 1/4, 3/4; no filter gives den = 0 and 1/2, 1/2.
+    D = np.array([[4.0, -1.0, -1.0, -2.0],
+                  [-1.0, 4.0, 0.0, 1.0],
+                  [-1.0, 0.0, 4.0, -1.0],
+                  [1.0, 1.0, -1.0, -4.0]])
+    strong = [[1, 2, 3], [0], [0], [1]]
+    P = _interp_rows(orc, D, strong, [-1, 1, 1, -1])
+    assert P[0, 0] == 0.75 and P[0, 1] == 0.25
+
+
+def test_interp_sign_filter_all_same_sign_lumps_the_f_neighbour(orc):
+    # every coupling of the strong F neighbour 3 to C_0 = {1, 2} has the sign of
+    # its diagonal (a_33 = 4, a_31 = 1, a_32 = 2): den = 0, so a_03 = -2 joins the
+    # diagonal: atil = 4 - 2 = 2, w_01 = -(-1) / 2 = 1/2, w_02 = -(-0.5) / 2 = 1/4.
+    D = np.array([[4.0, -1.0, -0.5, -2.0],
+                  [-1.0, 4.0, 0.0, 0.0],
+                  [-0.5, 0.0, 4.0, 0.0],
+                  [-2.0, 1.0, 2.0, 4.0]])
+    strong = [[1, 2, 3], [0], [0], [0]]
+    P = _interp_rows(orc, D, strong, [-1, 1, 1, -1])
+    assert P[0, 0] == 0.5 and P[0, 1] == 0.25
+
+
+def test_interp_sign_filter_zero_coupling_is_not_kept(orc):
+    # a stored zero a_31 = 0 has no sign opposite to a_33: it is dropped like a
+    # same-sign entry.  With a_32 = -2 kept: den = -2, num_2 = (-1)(-2)/(-2) = -1,
+    # atil = 4, w_01 = -(-1)/4 = 1/4, w_02 = -(-1 - 1)/4 = 1/2.
+    D = np.array([[4.0, -1.0, -1.0, -1.0],
+                  [-1.0, 4.0, 0.0, 0.0],
+                  [-1.0, 0.0, 4.0, 0.0],
+                  [-1.0, 0.0, -2.0, 4.0]])
+    M = sp.csr_matrix(D)
+    # store a_31 = 0 explicitly
+    indptr = np.array([0, 4, 6, 8, 12])
+    indices = np.array([0, 1, 2, 3, 0, 1, 0, 2, 0, 1, 2, 3], np.int32)
+    data = np.array([M[i, j] for i in range(4) for j in indices[indptr[i]:indptr[i + 1]]])
+    Ao = orc.as_csr(indptr, indices, data)
+    assert Ao.indices[Ao.indptr[3]:Ao.indptr[4]].tolist() == [0, 1, 2, 3]
+    S = orc.as_csr([0, 3, 4, 5, 6], np.array([1, 2, 3, 0, 0, 0], np.int32), None, (4, 4))
+    P = orc.to_scipy(orc.interp(Ao, S, np.array([-1, 1, 1, -1], np.int32))).toarray()
+    assert P[0, 0] == 0.25 and P[0, 1] == 0.5
+
+
+def test_l1_smoother_diagonal_is_the_absolute_row_sum(orc):
+    # mixed-sign rows: the l1 diagonal is sum_j |a_ij| (hand sums below), not
+    # |a_ii| and not the signed row sum
+    D = np.array([[4.0, -1.0, 0.5, 0.0, 0.0, 0.0],
+                  [-1.0, 5.0, -2.0, 0.25, 0.0, 0.0],
+                  [0.5, -2.0, -6.0, 1.0, 0.0, 0.0],
+                  [0.0, 0.25, 1.0, 3.0, -1.5, 0.0],
+                  [0.0, 0.0, 0.0, -1.5, 4.0, -1.0],
+                  [0.0, 0.0, 0.0, 0.0, -1.0, 2.0]])
+    expect = np.array([5.5, 8.25, 9.5, 5.75, 6.5, 3.0])
+    A = orc.from_scipy(sp.csr_matrix(D))
+    o = orc.Oracle(A, np.zeros(6, np.int32), block_size=1, amg_coarse_max=2)
+    assert o.n_amg_levels >= 2
+    np.testing.assert_array_equal(o.amg_level(0)["l1"], expect)
