@@ -83,8 +83,8 @@ typedef struct {
     int frelax_amg_pre, frelax_amg_post;  /* smoothing sweeps of that V-cycle, default 1, 1 */
     int cycle_post;           /* 0: pre-smoothing form eq. MGR-pre (Section 4 algorithm "MGR preconditioner
                                  with presmoothing", default); 1: post-smoothing form eq. MGR-post: the
-                                 coarse-grid correction from e = 0 first, then F-relaxation, then (level 0)
-                                 the global relaxation */
+                                 coarse-grid correction from e = 0 first, then the same smoother M_f as
+                                 the pre-smoothing form: (level 0) the global relaxation, then F-relaxation */
 } mgr_options;
 
 typedef struct {

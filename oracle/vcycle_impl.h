@@ -134,16 +134,16 @@ static void FN(mgr_cycle)(orc_handle *h, int l, const REAL *r, REAL *e) {
     for (int64_t i = 0; i < nU; ++i) e[i] = 0;
     if (h->o.cycle_post) {
         /* post-smoothing form, eq. MGR-post: the coarse-grid correction from e = 0
-         * first, then the smoother, whose two steps run in the reverse order of the
-         * pre-smoothing algorithm (F-relaxation, then the level-0 global relaxation) */
+         * first, then the same smoother M_f as in eq. MGR-pre, with its steps in the
+         * same order: the level-0 global relaxation, then the F-relaxation */
         FN(spmv)(&lv->R, VALS(lv->R, lv->Rf), r, rc);
         FN(mgr_cycle)(h, l + 1, rc, ec);
         FN(spmv_add)(&lv->P, VALS(lv->P, lv->Pf), ec, e);
-        FN(frelax)(h, lv, Av, dinv, r, e, tf, df);
         if (l == 0 && h->o.global_relax) {
             FN(residual)(&lv->A, Av, r, e, rho);
             FN(block_apply_add)(h, rho, e);
         }
+        FN(frelax)(h, lv, Av, dinv, r, e, tf, df);
     } else {
         /* (1) global relaxation e = blockdiag(A)^{-1} r (level 0 only) */
         if (l == 0 && h->o.global_relax) FN(block_apply_add)(h, r, e);

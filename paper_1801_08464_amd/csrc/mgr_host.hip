@@ -890,16 +890,17 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
     const bool global = l == 0 && h->o.global_relax;
     const double gbytes = (double)h->bs * h->bs * S * h->ncell + 2.0 * S * n;
     if (h->o.cycle_post) {
-        // eq. MGR-post: coarse-grid correction from e = 0, then the smoother in the
-        // reverse order of the pre-smoothing steps (F-relaxation, global relaxation)
+        // eq. MGR-post: coarse-grid correction from e = 0, then the smoother M_f of
+        // the pre-smoothing form with its steps in the same order (global
+        // relaxation at level 0, then F-relaxation)
         coarse_correction(r);
         csr<T>(h, 0, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
-        frelax(true);
         if (global) {
             fine_op<T>(h, 1, e, r, t);
             launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), t, e, true, s);
             acct(h, gbytes + S * n);
         }
+        frelax(true);
         return;
     }
     // (1) global relaxation with the cell blocks (level 0)

@@ -110,8 +110,9 @@ def test_two_level_ideal_operators_are_exact(orc, transpose):
 def _mgr_minv(orc, o, bs_inv, post=False):
     """M^{-1} of the recursive MGR V-cycle from the paper's propagator
     I - M_l^{-1} A_l = (I - P_l M_{l+1}^{-1} R_l A_l)(I - Q_l D_l^{-1} Q_l^T A_l)(I - B^{-1} A_0 at l = 0)
-    (eq. MGR-pre), or with post=True the reversed product of eq. MGR-post
-    (I - B^{-1} A_0 at l = 0)(I - Q_l D_l^{-1} Q_l^T A_l)(I - P_l M_{l+1}^{-1} R_l A_l),
+    (eq. MGR-pre), or with post=True eq. MGR-post, the same smoother factor
+    I - M_f^{-1} A after the coarse-grid correction:
+    (I - Q_l D_l^{-1} Q_l^T A_l)(I - B^{-1} A_0 at l = 0)(I - P_l M_{l+1}^{-1} R_l A_l),
     with AMG V(2,2) (or dense LU) below the last level."""
     L = o.n_mgr_levels
     nl = o.n_amg_levels
@@ -139,17 +140,31 @@ def _mgr_minv(orc, o, bs_inv, post=False):
         Ec = np.eye(n) - dense(orc, lv["P"]) @ mgr_minv(l + 1) @ dense(orc, lv["R"]) @ Al
         Ef = np.eye(n) - Q @ np.diag(lv["dinv"]) @ Q.T @ Al
         Eg = np.eye(n) - bs_inv @ Al if l == 0 else np.eye(n)
-        E = Eg @ Ef @ Ec if post else Ec @ Ef @ Eg
+        # I - M_f^{-1} A = Ef Eg in both forms (global relaxation first, then F-relaxation)
+        E = Ef @ Eg @ Ec if post else Ec @ Ef @ Eg
         return (np.eye(n) - E) @ np.linalg.inv(Al)
 
     return mgr_minv(0)
 
 
-@pytest.mark.parametrize("grid,post", [((4, 4), False), ((9, 9), False), ((4, 4), True), ((9, 9), True)])
-def test_vcycle_equals_closed_form_propagator(orc, grid, post):
+def _rho_first_labels(s):
+    """Labels that eliminate rho first (level 0), then S in every cell (level 1),
+    with p as the coarse grid.  The level-0 F rows then couple to other cells, so
+    the F-relaxation and the global relaxation do not commute (with the default
+    labels they do: the single-phase S rows hold only their own diagonal)."""
+    lab = np.empty(s.n, np.int32)
+    lab[0::3], lab[1::3], lab[2::3] = 2, 0, 1
+    return lab
+
+
+@pytest.mark.parametrize("grid,post,labels", [((4, 4), False, "default"), ((9, 9), False, "default"),
+                                              ((4, 4), True, "default"), ((9, 9), True, "default"),
+                                              ((5, 4), False, "rho_first"), ((5, 4), True, "rho_first")])
+def test_vcycle_equals_closed_form_propagator(orc, grid, post, labels):
     s = make_system(grid, 1.0, "disk", 0.4, seed=2)
     A = orc.as_csr(s.indptr, s.indices, s.data)
-    o = orc.Oracle(A, s.labels, cycle_post=int(post))
+    lab = s.labels if labels == "default" else _rho_first_labels(s)
+    o = orc.Oracle(A, lab, cycle_post=int(post))
     binv = o.block_inverses().reshape(-1, 3, 3)
     B = np.zeros((s.n, s.n))
     for c in range(s.n_cells):
