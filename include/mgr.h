@@ -243,6 +243,24 @@ int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double 
 int mgr_ncp_jacobian(const mgr_csr *L, const double *henry, const int32_t *labels, int32_t *row_ptr,
                      int32_t *col_idx, double *values, int64_t capacity, int64_t *nnz, void *stream);
 
+/*
+ * mgr_ncp_eval_noalloc: mgr_ncp_eval for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as mgr_ncp_eval; it
+ * calls no hipMalloc, hipFree or allocating library routine.  Its device scratch
+ * (the residual norm's partial sums, the norm and the two cell counters) is a
+ * file-scope device array of 16 KiB that each GPU the library runs on holds
+ * until the process ends; the need is (blocks of the norm reduction + 1)
+ * doubles and two ints (at most 8,208 bytes with the library's reduction grid,
+ * whatever n), and a call that would need more returns MGR_E_INVALID with the
+ * sizes in mgr_last_error(NULL).  The counters are cleared by a kernel on every
+ * call.  All calls on one GPU share that array: calls that overlap on one GPU
+ * (different streams, or threads) race and must be serialised by the caller.
+ */
+int mgr_ncp_eval_noalloc(const mgr_csr *L, const double *henry, const double *f, double *u, const double *du,
+                         double alpha, double *R, int32_t *labels, double *rnorm, int64_t *nactive,
+                         int64_t *nchanged, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

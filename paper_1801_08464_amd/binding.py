@@ -18,7 +18,8 @@ E_INVALID, E_ZERO_FDIAG, E_SINGULAR_BLOCK, E_BREAKDOWN, E_HIP, E_OOM = -1, -2, -
 EXPORTS = [
     "mgr_default_options", "mgr_setup", "mgr_solve", "mgr_pattern_outer", "mgr_apply_preconditioner", "mgr_spmv",
     "mgr_destroy", "mgr_status_string", "mgr_last_error", "mgr_num_levels", "mgr_get_matrix", "mgr_get_vector",
-    "mgr_set_kernel_timing", "mgr_kernel_time", "mgr_ncp_eval", "mgr_ncp_jacobian", "mgr_update_values",
+    "mgr_set_kernel_timing", "mgr_kernel_time", "mgr_ncp_eval", "mgr_ncp_jacobian", "mgr_ncp_eval_noalloc",
+    "mgr_update_values",
 ]
 
 
@@ -84,6 +85,8 @@ def load_library(build_if_missing: bool = True):
     L.mgr_set_kernel_timing.argtypes = [vp, i32]
     L.mgr_kernel_time.argtypes = [vp, i32, P(C.c_double), P(i64), P(C.c_double)]
     L.mgr_ncp_eval.argtypes = [P(MgrCsr), vp, vp, vp, vp, C.c_double, vp, vp, P(C.c_double), P(i64), P(i64), vp]
+    L.mgr_ncp_eval_noalloc.argtypes = [P(MgrCsr), vp, vp, vp, vp, C.c_double, vp, vp, P(C.c_double), P(i64), P(i64),
+                                       vp]
     L.mgr_ncp_jacobian.argtypes = [P(MgrCsr), vp, vp, vp, vp, vp, i64, P(i64), vp]
     _lib = L
     return L

@@ -1643,6 +1643,90 @@ int mgr_ncp_eval(const mgr_csr *L, const double *henry, const double *f, double 
     }
 }
 
+}  // extern "C"
+
+// Allocation-free form of mgr_ncp_eval.  Its device scratch (the partial sums
+// of the residual norm, the norm itself and the two cell counters) lives in a
+// file-scope array instead of the stream-ordered pool.  On the host the name
+// `scratch` is only a stand-in; the array's device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only
+// that address is ever handed to kernels.
+static constexpr size_t kStaticScratchBytes = 16384;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (resolved on first use).
+int static_scratch(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        g_err = "no current HIP device";
+        return MGR_E_HIP;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            g_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return MGR_E_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MGR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mgr_ncp_eval_noalloc(const mgr_csr *L, const double *henry, const double *f, double *u, const double *du,
+                         double alpha, double *R, int32_t *labels, double *rnorm, int64_t *nactive,
+                         int64_t *nchanged, void *stream) {
+    if (check_ncp_csr(L) != MGR_OK) return MGR_E_INVALID;
+    if (!henry || !f || !u || !R || !labels) {
+        g_err = "null argument";
+        return MGR_E_INVALID;
+    }
+    const int64_t n = L->n, ncell = n / 3;
+    const int nblk = red_blocks(n);
+    // layout: the norm's partial sums, then the norm, then the two counters
+    const size_t need = ((size_t)nblk + 1) * sizeof(double) + 2 * sizeof(int);
+    if (need > kStaticScratchBytes || nblk > kRedBlocks) {
+        g_err = "mgr_ncp_eval_noalloc: needs " + std::to_string(need) + " bytes of static scratch, capacity " +
+                std::to_string(kStaticScratchBytes);
+        return MGR_E_INVALID;
+    }
+    void *base = nullptr;
+    if (const int rc = static_scratch(&base); rc != MGR_OK) return rc;
+    double *part = static_cast<double *>(base);
+    double *norm = part + nblk;
+    int *cnt = reinterpret_cast<int *>(norm + 1);
+    const hipStream_t s = (hipStream_t)stream;
+    if (du) launch_axpy_inplace(n, alpha, du, u, s);
+    launch_fill_i32(cnt, 0, 2, s);  // a fill kernel: the counters start at zero on every call
+    launch_ncp_eval(ncell, L->row_ptr, L->col_idx, L->values, henry, f, u, R, labels, cnt, cnt + 1, s);
+    launch_norm_part(n, R, part, s);
+    launch_norm_fin(nblk, part, norm, s);
+    double rn = 0.0;
+    int na[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(&rn, norm, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(na, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        g_err = std::string("mgr_ncp_eval_noalloc: ") + hipGetErrorString(e);
+        return MGR_E_HIP;
+    }
+    if (rnorm) *rnorm = rn;
+    if (nactive) *nactive = na[0];
+    if (nchanged) *nchanged = na[1];
+    return std::isfinite(rn) ? MGR_OK : MGR_E_BREAKDOWN;
+}
+
 int mgr_ncp_jacobian(const mgr_csr *L, const double *henry, const int32_t *labels, int32_t *row_ptr,
                      int32_t *col_idx, double *values, int64_t capacity, int64_t *nnz, void *stream) {
     if (check_ncp_csr(L) != MGR_OK) return MGR_E_INVALID;
