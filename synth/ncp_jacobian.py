@@ -65,6 +65,15 @@ class NCPSystem:
     def scipy(self) -> sp.csr_matrix:
         return sp.csr_matrix((self.data, self.indices, self.indptr), shape=(self.n, self.n))
 
+    def fingerprint(self) -> str:
+        """SHA-256 over the bytes of the CSR arrays, the labels and b (to check
+        that a stored result belongs to this very input)."""
+        import hashlib
+        h = hashlib.sha256()
+        for a in (self.indptr, self.indices, self.data, self.labels, self.b):
+            h.update(np.ascontiguousarray(a).tobytes())
+        return h.hexdigest()
+
 
 # The five workloads: grid, permeability contrast sigma, two-phase region shape and
 # fraction, seed, number of observation cells.

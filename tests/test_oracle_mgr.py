@@ -4,6 +4,7 @@ the pre-smoothing propagator eq. MGR-pre) and the closed forms of the three
 reductions of Section 5 on the generator's Jacobian (CPU only)."""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 from synth import make_system
 
@@ -280,3 +281,38 @@ def test_introspection_of_coarse_and_fblock_hierarchies(orc):
     np.testing.assert_allclose(L @ np.triu(flu), Af[fperm], rtol=1e-12, atol=1e-12 * np.abs(Af).max())
     with pytest.raises(IndexError):
         o.ff_level(0, 0)
+
+
+def test_level2_fblock_has_no_strong_connections(orc):
+    # Section 6.2 relaxes the F-points of every reduction after the first with one
+    # AMG V(1,1)-cycle on A_FF.  At the last reduction (S in two-phase cells) of
+    # this Jacobian, A_FF has a negative diagonal and only negative off-diagonal
+    # entries, so no coupling is strong in the classical (sign-aware) sense: PMIS
+    # makes every point F and the F-block "hierarchy" is its coarsest level alone,
+    # a direct solve of A_FF.  Below the dense limit that is what the AMG option
+    # does (and it takes more GMRES iterations than one Jacobi sweep); above it
+    # the setup stops because the coarsening stalls.
+    s = make_system((20, 20, 20), 2.0, "ball", 0.3, seed=4)
+    A = orc.as_csr(s.indptr, s.indices, s.data)
+    o = orc.Oracle(A, s.labels, frelax_amg_mask=2)
+    d = o.mgr_level(2)
+    M = orc.to_scipy(d["A"]).tocsr()
+    F = d["flist"]
+    Aff = M[F][:, F].tocsr()
+    Aff.sort_indices()
+    dg = Aff.diagonal()
+    off = Aff - sp.diags(dg)
+    off.eliminate_zeros()
+    assert np.all(dg < 0) and off.nnz > 0 and np.all(off.data < 0)
+    S = orc.strength(orc.from_scipy(Aff))
+    assert S.indices.shape[0] == 0
+    jac = o.solve(s.b, 1e-8)
+    o.close()
+    o6 = orc.Oracle(A, s.labels, frelax_amg_mask=6)
+    assert o6.n_ff_levels(2) == 1
+    amg = o6.solve(s.b, 1e-8)
+    o6.close()
+    assert jac.status == 0 and amg.status == 0 and amg.iterations > jac.iterations, (jac.iterations, amg.iterations)
+    big = make_system((40, 40, 40), 2.0, "ball", 0.3, seed=4)
+    with pytest.raises(orc.OracleError, match="stalled"):
+        orc.Oracle(orc.as_csr(big.indptr, big.indices, big.data), big.labels, frelax_amg_mask=6)
