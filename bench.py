@@ -24,11 +24,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MGR-GMRES unknowns/s to 1e-8 rel. residual, FP64 vs mixed; V-cycle % HBM peak"
 HBM_PEAK_GBS = 8000.0
-# The paper's setup for its phase-transition runs (Section 6.2): non-injective R/P
+# Solver options after Section 6.2's phase-transition runs: non-injective R/P
 # (eq. non_injective_rp) at every reduction, Jacobi F-relaxation at the first
 # reduction, one AMG V(1,1)-cycle on A_FF at the second, AMG V(2,2) on the coarse
-# grid.  The last (constraint) reduction keeps Jacobi: its F-block has no strong
-# couplings for AMG to coarsen.
+# grid.  Section 6.2 also puts an AMG V(1,1) at the last (constraint) reduction;
+# here that F-block has a negative diagonal and only negative couplings, so its
+# classical strength graph is empty and an AMG could not coarsen it: it keeps
+# one Jacobi sweep.
 SOLVER_OPTS = dict(frelax_amg_mask=2, frelax_amg_pre=1, frelax_amg_post=1)
 
 
@@ -91,9 +93,11 @@ def run_form(s, dev, form, steps, warmup, tol, timing=False):
     vtime = [k.kernel_time(1) for k in keep if hasattr(k, "kernel_time")] if timing else []
     stime = [k.kernel_time(2) for k in keep if hasattr(k, "kernel_time")] if timing else []
     err = None
+    x_host = None
     if form != "adjoint":
         xt = torch.as_tensor(s.x_true, device=dev)
         err = float(torch.linalg.norm(x - xt) / torch.linalg.norm(xt))
+        x_host = x.cpu().numpy()
     for k in keep:
         if hasattr(k, "close"):
             k.close()
@@ -115,6 +119,7 @@ def run_form(s, dev, form, steps, warmup, tol, timing=False):
     )
     if err is not None:
         out["rel_error_vs_x_true"] = err
+        out["_x"] = x_host
     def summary(rec):
         ms = sum(k[0] for k in rec)
         cnt = sum(k[1] for k in rec)
@@ -201,30 +206,112 @@ def run_newton(dev, cfg, steps, warmup):
                          "step = the whole Newton solve")
 
 
-def cpu_baseline(cfg, iterations):
-    """The oracle (plain C, one thread) on the same system as the GPU step, within
-    a bounded CPU budget: its whole setup, then its first restart cycle of 30
-    GMRES iterations; the solve time is scaled to the `iterations` the workload
-    takes (all cycles but the last are full 30-step cycles, so the cycle's mean
-    orthogonalisation cost carries over)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def oracle_job(cfg, precision, out_prefix):
+    """The oracle (plain C, one thread) on the benchmark's system, the whole job:
+    setup, then GMRES to the tolerance.  Runs in a process of its own, started
+    before the GPU forms; writes its timings and counts (JSON) and x (.npy)."""
+    import numpy as np
+
     from oracle import oracle as O
     from synth import make_config
     s = make_config(cfg)
     A = O.as_csr(s.indptr, s.indices, s.data)
-    cycle = 30
+    log(f"oracle {precision}: n={s.n}, setup ...")
     t0 = time.perf_counter()
-    o = O.Oracle(A, s.labels, max_iter=cycle, **SOLVER_OPTS)
+    o = O.Oracle(A, s.labels, precision=1 if precision == "fp32_apply" else 0, **SOLVER_OPTS)
     t1 = time.perf_counter()
+    log(f"oracle {precision}: setup {t1 - t0:.1f} s, solving ...")
     r = o.solve(s.b, 1e-8)
     t2 = time.perf_counter()
     o.close()
-    setup, solve = t1 - t0, t2 - t1
-    est = setup + solve * iterations / r.iterations
-    return dict(value=s.n / est, unit="unknowns/s", cores=1, kind="oracle",
-                sample=f"oracle (FP64, 1 thread) on the same {'x'.join(map(str, s.grid))} system: full setup "
-                       f"{setup:.1f} s, then the first {r.iterations} GMRES iterations {solve:.1f} s; solve scaled "
-                       f"to the {iterations} iterations of the workload: {est:.0f} s for the whole job",
-                cpu=platform.processor() or platform.machine())
+    log(f"oracle {precision}: {r.iterations} iterations in {t2 - t1:.1f} s (status {r.status})")
+    np.save(out_prefix + ".npy", r.x)
+    with open(out_prefix + ".json", "w") as f:
+        json.dump(dict(precision=precision, status=int(r.status), iterations=int(r.iterations),
+                       rel_residual=float(r.rel_residual), setup_s=t1 - t0, solve_s=t2 - t1), f)
+
+
+def start_oracle_jobs(cfg):
+    import subprocess
+    import tempfile
+    tmp = tempfile.mkdtemp(prefix="mgr_bench_oracle_")
+    jobs = {}
+    for prec in ("fp64", "fp32_apply"):
+        prefix = os.path.join(tmp, prec)
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-job", prec, "--config", str(cfg),
+               "--oracle-out", prefix]
+        jobs[prec] = (subprocess.Popen(cmd, env=dict(os.environ, OMP_NUM_THREADS="1")), prefix)
+    return tmp, jobs
+
+
+def finish_oracle_jobs(tmp, jobs):
+    import shutil
+
+    import numpy as np
+    out = {}
+    for prec, (proc, prefix) in jobs.items():
+        rc = proc.wait()
+        if rc != 0:
+            raise RuntimeError(f"oracle job {prec} failed with status {rc}")
+        with open(prefix + ".json") as f:
+            rec = json.load(f)
+        rec["x"] = np.load(prefix + ".npy")
+        out[prec] = rec
+    shutil.rmtree(tmp, ignore_errors=True)
+    return out
+
+
+def oracle_parity(s, dev, forms, orc):
+    """Iterations against the oracle's (within one), and the solution error against
+    the FP64 oracle's x: after exactly the oracle's number of iterations (tol = 0,
+    the FP64 form) and, for information, of each form's own converged solve."""
+    import numpy as np
+    import torch
+
+    from paper_1801_08464_amd.solver import MGRSolver
+    xo = orc["fp64"]["x"]
+    nxo = float(np.linalg.norm(xo))
+    for form, key in (("fp64", "fp64"), ("mixed", "fp32_apply")):
+        if form not in forms:
+            continue
+        f, rec = forms[form], orc[key]
+        f["oracle"] = dict(mode="FP64" if key == "fp64" else "FP32 apply", iterations=rec["iterations"],
+                           status=rec["status"], rel_residual=rec["rel_residual"])
+        f["iterations_minus_oracle"] = f["iterations"] - rec["iterations"]
+        f["converged_rel_error_vs_oracle"] = float(np.linalg.norm(f["_x"] - xo) / nxo)
+    if "fp64" in forms:
+        its = orc["fp64"]["iterations"]
+        g = MGRSolver(torch.as_tensor(s.indptr, device=dev), torch.as_tensor(s.indices, device=dev),
+                      torch.as_tensor(s.data, device=dev), torch.as_tensor(s.labels, device=dev),
+                      max_iter=its, **SOLVER_OPTS)
+        xm, im = g.solve(torch.as_tensor(s.b, device=dev), 0.0)
+        g.close()
+        err = float(np.linalg.norm(xm.cpu().numpy() - xo) / nxo)
+        forms["fp64"]["rel_error_vs_oracle"] = err
+        forms["fp64"]["rel_error_vs_oracle_mode"] = f"matched iterations ({im.iterations}, tol 0)"
+        log(f"fp64: matched-iteration error vs the oracle {err:.2e} at {im.iterations} iterations")
+
+
+def cpu_baseline(s, rec):
+    """The oracle's whole job (setup + solve to 1e-8), measured on this host."""
+    t = rec["setup_s"] + rec["solve_s"]
+    return dict(value=s.n / t, unit="unknowns/s", cores=1, kind="oracle",
+                sample=f"the whole oracle job on the same {'x'.join(map(str, s.grid))} system, measured (not "
+                       f"scaled): setup {rec['setup_s']:.1f} s, then GMRES to 1e-8 in {rec['iterations']} iterations "
+                       f"{rec['solve_s']:.1f} s, FP64, 1 thread (the FP32-apply oracle ran beside it in a process "
+                       "of its own)",
+                seconds=t, cpu=cpu_model())
 
 
 # R/P and cycle variants of the MGR preconditioner (Section 4): each changes one
@@ -286,9 +373,14 @@ def main():
     ap.add_argument("--variants", default=None,
                     help="comma-separated configs: time the R/P and cycle variants of the preconditioner "
                          "against the default on them (prints one JSON line with the table)")
+    ap.add_argument("--oracle-job", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-out", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy kernel (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.oracle_job:
+        oracle_job(args.config, args.oracle_job, args.oracle_out)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -311,6 +403,10 @@ def main():
         torch.mul(src, 1.0, out=dst)  # reads and writes exactly 512 MiB each
         torch.cuda.synchronize()
         del src, dst
+    oracle_run = None
+    if not args.no_cpu_baseline and "fp64" in args.forms.split(","):
+        # the oracle's whole job runs on the host cores beside the GPU forms
+        oracle_run = start_oracle_jobs(args.config)
     t = time.perf_counter()
     s = make_config(args.config)
     log(f"config {args.config}: n={s.n} nnz={s.nnz} generated in {time.perf_counter() - t:.1f}s")
@@ -363,9 +459,13 @@ def main():
                        for k, v in forms.items() if "vcycle" in v and k not in ("adjoint", "newton")},
         "forms": forms,
     }
-    if not args.no_cpu_baseline and "fp64" in forms:
-        log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(args.config, forms["fp64"]["iterations"])
+    if oracle_run is not None:
+        log("waiting for the oracle ...")
+        orc = finish_oracle_jobs(*oracle_run)
+        oracle_parity(s, dev, forms, orc)
+        line["cpu_baseline"] = cpu_baseline(s, orc["fp64"])
+    for f in forms.values():
+        f.pop("_x", None)
     print(json.dumps(line))
 
 

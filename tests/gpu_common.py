@@ -25,3 +25,22 @@ def assert_same_csr(gpu_mat, orc_mat, what):
 
 def small_system(grid=(7, 5), seed=3, sigma=1.5, frac=0.4, region="disk"):
     return make_system(grid, sigma, region, frac, seed)
+
+
+# Element-wise V-cycle parity (HIP path against the oracle on the same input r).
+# FP64: the two sides differ by rounding order only (tree-reduced row sums on
+# the small AMG levels, sequential ones in the oracle), a few ulps per entry
+# carried through the levels.  FP32 (mixed form, against the oracle's FP32-apply
+# mode on the same once-rounded values): the same rounding-order differences at
+# unit roundoff 6e-8 instead of 1.1e-16.
+VCYCLE_TOL = {"fp64": (1e-10, 1e-12), "mixed": (2e-4, 2e-6)}
+
+
+def assert_vcycle_close(z, ze, precision, what=""):
+    rtol, atol = VCYCLE_TOL[precision]
+    scale = float(np.abs(ze).max())
+    d = np.abs(z - ze)
+    worst = float((d / (rtol * np.abs(ze) + atol * scale)).max()) if ze.size else 0.0
+    print(f"[vcycle {what} {precision}] max |dz| / max |z| = {d.max() / scale:.2e}, "
+          f"worst entry at {worst:.2e} of the bound", flush=True)
+    np.testing.assert_allclose(z, ze, rtol=rtol, atol=atol * scale, err_msg=what)
