@@ -115,7 +115,18 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
         }
         __syncthreads();
         const int lo = a > base ? a : base, hi = b < lim ? b : lim;
-        for (int p = lo; p < hi; ++p) acc = acc + sh[p - base];
+        // the row's products in ascending order; eight LDS reads are issued
+        // before their additions so that a long row waits for LDS once per eight
+        // entries instead of once per entry
+        int p = lo;
+        for (; p + 8 <= hi; p += 8) {
+            T s[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s[u] = sh[p - base + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = acc + s[u];
+        }
+        for (; p < hi; ++p) acc = acc + sh[p - base];
         __syncthreads();
     }
     if (row < re) {
@@ -306,25 +317,38 @@ __global__ void __launch_bounds__(256) k_lu_solve(int64_t n, const double *__res
     for (int64_t i = tid; i < n; i += blockDim.x) x[i] = (T)y[i];
 }
 
-// the same substitutions for n <= 64 in one wavefront: the factors are copied to
-// LDS first, lane i holds y[i] and y[k] is broadcast by a shuffle, so there are
-// no workgroup barriers (same operations in the same order as the workgroup kernel)
+// Broadcast of lane k's double to the whole wavefront (k uniform): two
+// v_readlane, no LDS round trip as a shuffle would take.
+__device__ inline double lane_bcast(double v, int k) {
+    const long long u = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, k);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), k);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// the same substitutions for n <= 64 in one wavefront: four wavefronts copy the
+// factors to LDS, then lane i of the first holds y[i] and y[k] is broadcast
+// from lane k, so the substitutions need no workgroup barrier (same operations
+// in the same order as the workgroup kernel)
 template <typename T>
-__global__ void __launch_bounds__(kWave) k_lu_solve_wave(int n, const double *__restrict__ lu,
-                                                         const int32_t *__restrict__ perm, const T *__restrict__ b,
-                                                         T *__restrict__ x) {
+__global__ void __launch_bounds__(256) k_lu_solve_wave(int n, const double *__restrict__ lu,
+                                                       const int32_t *__restrict__ perm, const T *__restrict__ b,
+                                                       T *__restrict__ x) {
     __shared__ double L[kWave * kWave];
-    const int l = threadIdx.x;
-    for (int q = l; q < n * n; q += kWave) L[q] = lu[q];
-    double y = l < n ? (double)b[perm[l]] : 0.0;
+    const int t = threadIdx.x;
+    double y = t < n ? (double)b[perm[t]] : 0.0;
+#pragma unroll 4
+    for (int q = t; q < n * n; q += 256) L[q] = lu[q];
     __syncthreads();
+    if (t >= kWave) return;
+    const int l = t;
     for (int k = 0; k < n; ++k) {
-        const double yk = __shfl(y, k);
+        const double yk = lane_bcast(y, k);
         if (l > k && l < n) y = y - L[l * n + k] * yk;
     }
     for (int k = n - 1; k >= 0; --k) {
         if (l == k) y = y / L[k * n + k];
-        const double yk = __shfl(y, k);
+        const double yk = lane_bcast(y, k);
         if (l < k) y = y - L[l * n + k] * yk;
     }
     if (l < n) x[l] = (T)y;
@@ -491,7 +515,7 @@ void launch_scatter_set(int64_t n, const int32_t *map, const T *d, T *e, hipStre
 template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s) {
     if (n <= 0) return;
-    if (n <= kWave) k_lu_solve_wave<T><<<1, kWave, 0, s>>>((int)n, lu, perm, b, x);
+    if (n <= kWave) k_lu_solve_wave<T><<<1, 256, 0, s>>>((int)n, lu, perm, b, x);
     else k_lu_solve<T><<<1, BT, (size_t)n * sizeof(double), s>>>(n, lu, perm, b, x);
 }
 
