@@ -140,7 +140,7 @@ def run_form(s, dev, form, steps, warmup, tol, timing=False):
 
 FINE_RECORD = os.path.join(ROOT, "profiles", "k_csell_128cube_fp64_hbm_traffic.md")
 FINE_SOURCE = os.path.join(ROOT, "paper_1801_08464_amd", "csrc", "k_fine.hip")
-SWEEP_RECORD = os.path.join(ROOT, "profiles", "k_csr_stream_coarse_sweep_128cube_fp64_hbm_traffic.md")
+SWEEP_RECORD = os.path.join(ROOT, "profiles", "k_jag_stream_coarse_sweep_128cube_fp64_hbm_traffic.md")
 SWEEP_SOURCE = os.path.join(ROOT, "paper_1801_08464_amd", "csrc", "k_solve.hip")
 
 
@@ -430,8 +430,8 @@ def main():
     cs = main_form.get("coarse_sweep")
     # the dominant kernel of a step: the l1-Jacobi sweep on the coarse-grid matrix
     # (three launches per iteration); the fine-level operator is reported beside it
-    roof = roofline(cs, "k_csr_stream<double, 3, 256, 5120>: l1-Jacobi sweep on the coarse-grid matrix "
-                        "(AMG level 0 of the pressure system)", SWEEP_RECORD, SWEEP_SOURCE,
+    roof = roofline(cs, "k_jag_stream<double, 3, 4864>: l1-Jacobi sweep on the coarse-grid matrix "
+                        "(AMG level 0 of the pressure system, row-block jagged copy)", SWEEP_RECORD, SWEEP_SOURCE,
                     args.config) if cs else None
     roof_fine = roofline(fk, "k_csell: level-0 sliced-ELL SpMV / residual (the GMRES operator)", FINE_RECORD,
                          FINE_SOURCE, args.config) if fk else None

@@ -12,15 +12,16 @@ namespace {
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 
 // Workgroups are dealt to the 8 XCDs round-robin.  Renumber them so that each
-// XCD takes kXcdGroup consecutive row blocks before moving on (64 blocks of 256
-// rows: one 128 x 128 grid plane, whose neighbours' x values then stay in that
-// XCD's L2); a tail shorter than 8 groups keeps the plain order.
-constexpr int64_t kXcdGroup = 64;
+// XCD takes G consecutive row blocks before moving on (G blocks of kXcdGroupRows
+// rows in all: one 128 x 128 grid plane, whose neighbours' x values then stay in
+// that XCD's L2); a tail shorter than 8 groups keeps the plain order.
+constexpr int64_t kXcdGroupRows = 16384;
+template <int64_t G>
 __device__ inline int64_t xcd_grouped_block() {
-    const int64_t b = blockIdx.x, span = 8 * kXcdGroup;
+    const int64_t b = blockIdx.x, span = 8 * G;
     if (b >= (int64_t)gridDim.x / span * span) return b;
     const int64_t xcd = b % 8, i = b / 8;
-    return ((i / kXcdGroup) * 8 + xcd) * kXcdGroup + i % kXcdGroup;
+    return ((i / G) * 8 + xcd) * G + i % G;
 }
 
 // CSR "stream" SpMV: a workgroup owns ROWS consecutive rows.  Their nonzeros are
@@ -67,25 +68,28 @@ struct RowIn {
     }
 };
 
-template <typename T, int MODE, int ROWS, int LDSN>
-__global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
-                                                     const int32_t *__restrict__ ci, const T *__restrict__ v,
-                                                     const T *__restrict__ x, const T *__restrict__ r,
-                                                     const T *__restrict__ d, T *__restrict__ y,
-                                                     T *__restrict__ y2) {
-    constexpr int B = LDSN / ROWS;  // entries per thread per pass
+template <typename T, int MODE, int ROWS, int NT, int LDSN>
+__global__ void __launch_bounds__(NT) k_csr_stream(int64_t nrows, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci, const T *__restrict__ v,
+                                                   const T *__restrict__ x, const T *__restrict__ r,
+                                                   const T *__restrict__ d, T *__restrict__ y,
+                                                   T *__restrict__ y2) {
+    static_assert(NT >= ROWS && LDSN % NT == 0, "stream kernel shape");
+    constexpr int B = LDSN / NT;  // entries per thread per pass
     __shared__ T sh[LDSN];
     const int tid = threadIdx.x;
-    const int64_t rb = xcd_grouped_block() * ROWS;
+    const int64_t rb = xcd_grouped_block<kXcdGroupRows / ROWS>() * ROWS;
     const int64_t re = rb + ROWS < nrows ? rb + ROWS : nrows;
+    // threads below ROWS own a row each; all NT threads load and multiply
     const int64_t row = rb + tid;
+    const bool owner = tid < ROWS && row < re;
     const int p0 = rp[rb], p1 = rp[re];
     // the row's output operands: loaded up front in FP32 (the registers are
     // there), after the passes in FP64 (where they would cost a wave per SIMD)
     constexpr bool kEarlyRowIn = sizeof(T) == 4;
     int a = 0, b = 0;
     RowIn<T, MODE> in;
-    if (row < re) {
+    if (owner) {
         a = rp[row];
         b = rp[row + 1];
         if (kEarlyRowIn) in.load(row, x, r, d, y);
@@ -97,7 +101,7 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
         const int lim = base + LDSN < p1 ? base + LDSN : p1;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            const int p = base + u * ROWS + tid;
+            const int p = base + u * NT + tid;
             j[u] = p < lim ? __builtin_nontemporal_load(ci + p) : -1;
             av[u] = p < lim ? __builtin_nontemporal_load(v + p) : (T)0;
         }
@@ -110,7 +114,7 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
         for (int u = 0; u < B; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            const int p = base + u * ROWS + tid;
+            const int p = base + u * NT + tid;
             if (p < lim) sh[p - base] = av[u] * xv[u];
         }
         __syncthreads();
@@ -129,9 +133,158 @@ __global__ void __launch_bounds__(ROWS) k_csr_stream(int64_t nrows, const int32_
         for (; p < hi; ++p) acc = acc + sh[p - base];
         __syncthreads();
     }
-    if (row < re) {
+    if (owner) {
         if (!kEarlyRowIn) in.load(row, x, r, d, y);
         in.store(row, acc, y, y2);
+    }
+}
+
+// The same products and row sums over a matrix's row-block jagged copy (Jag):
+// the entries of a block of kJagRows rows are streamed in passes of LDSN as in
+// the CSR stream kernel, but in slot order, so the lanes of a wavefront gather x
+// at one stencil slot of consecutive rows.  Thread s owns the row of rank s and
+// adds its products in ascending slot (= ascending column) order: the sums are
+// those of the CSR stream kernel, bit for bit.  The block's slot table sits in
+// LDS; a row's entry k is at st[k] + s, so the owner threads read consecutive
+// LDS words.
+template <typename T, int MODE, int LDSN>
+__global__ void __launch_bounds__(kJagRows) k_jag_stream(int64_t nrows, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ jci, const T *__restrict__ jv,
+                                                         const int32_t *__restrict__ jrows,
+                                                         const int32_t *__restrict__ bst,
+                                                         const int32_t *__restrict__ st, const T *__restrict__ x,
+                                                         const T *__restrict__ r, const T *__restrict__ d,
+                                                         T *__restrict__ y, T *__restrict__ y2) {
+    constexpr int NT = kJagRows;
+    constexpr int B = LDSN / NT;
+    __shared__ T sh[LDSN];
+    __shared__ int sst[kJagMaxSlots + 1];
+    const int tid = threadIdx.x;
+    const int64_t blk = xcd_grouped_block<kXcdGroupRows / kJagRows>();
+    const int64_t rb = blk * NT;
+    const int64_t re = rb + NT < nrows ? rb + NT : nrows;
+    const int p0 = rp[rb];
+    const int total = rp[re] - p0;
+    const int t0 = bst[blk], nsl = bst[blk + 1] - t0;  // maxlen + 1 slot starts
+    for (int k = tid; k < nsl; k += NT) sst[k] = st[t0 + k];
+    const bool owner = rb + tid < re;
+    const int64_t row = owner ? jrows[rb + tid] : 0;
+    __syncthreads();
+    // the owner's row length: the number of slots holding more than tid rows
+    int len = 0;
+    if (owner) {
+        int lo = 0, hi = nsl - 1;  // slots [0, hi) all have count > tid iff ...
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sst[mid + 1] - sst[mid] > tid) lo = mid + 1;
+            else hi = mid;
+        }
+        len = lo;
+    }
+    constexpr bool kEarlyRowIn = sizeof(T) == 4;
+    RowIn<T, MODE> in;
+    if (owner && kEarlyRowIn) in.load(row, x, r, d, y);
+    T acc = 0;
+    int kc = 0;
+    for (int w0 = 0; w0 < total; w0 += LDSN) {
+        const int w1 = w0 + LDSN < total ? w0 + LDSN : total;
+        int j[B];
+        T av[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int q = w0 + u * NT + tid;
+            j[u] = q < w1 ? __builtin_nontemporal_load(jci + p0 + q) : -1;
+            av[u] = q < w1 ? __builtin_nontemporal_load(jv + p0 + q) : (T)0;
+        }
+        T xv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) xv[u] = j[u] >= 0 ? x[j[u]] : (T)0;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int q = w0 + u * NT + tid;
+            if (q < w1) sh[q - w0] = av[u] * xv[u];
+        }
+        __syncthreads();
+        // this row's entries inside [w0, w1), in ascending slot order, eight at a time
+        while (kc + 8 <= len && sst[kc + 7] + tid < w1) {
+            int q[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) q[u] = sst[kc + u] + tid - w0;
+            T v8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v8[u] = sh[q[u]];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = acc + v8[u];
+            kc += 8;
+        }
+        while (kc < len && sst[kc] + tid < w1) {
+            acc = acc + sh[sst[kc] + tid - w0];
+            ++kc;
+        }
+        __syncthreads();
+    }
+    if (owner) {
+        if (!kEarlyRowIn) in.load(row, x, r, d, y);
+        in.store(row, acc, y, y2);
+    }
+}
+
+// Jagged copy, first pass: cnt[b] = longest row of block b + 1.
+__global__ void __launch_bounds__(kJagRows) k_jag_count(int64_t nrows, const int32_t *__restrict__ rp,
+                                                        int32_t *__restrict__ cnt) {
+    __shared__ int sm[kJagRows / kWave];
+    const int64_t rb = (int64_t)blockIdx.x * kJagRows, i = rb + threadIdx.x;
+    int len = i < nrows ? rp[i + 1] - rp[i] : 0;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const int y = __shfl_xor(len, o);
+        len = y > len ? y : len;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) sm[threadIdx.x / kWave] = len;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int w = 0; w < kJagRows / kWave; ++w) m = sm[w] > m ? sm[w] : m;
+        cnt[blockIdx.x] = m + 1;
+    }
+}
+
+// Jagged copy, second pass (bst = exclusive scan of the counts): ranks (longer
+// rows first, ties by row), slot tables st[k] = sum over the block's rows of
+// min(len, k), and the entries in slot order.
+__global__ void __launch_bounds__(kJagRows) k_jag_fill(int64_t nrows, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                       const int32_t *__restrict__ bst, int32_t *__restrict__ st,
+                                                       int32_t *__restrict__ jrows, int32_t *__restrict__ jci,
+                                                       double *__restrict__ jv) {
+    __shared__ int slen[kJagRows];
+    __shared__ int sst[kJagMaxSlots + 1];
+    const int t = threadIdx.x;
+    const int64_t rb = (int64_t)blockIdx.x * kJagRows, i = rb + t;
+    const int nr = nrows - rb < kJagRows ? (int)(nrows - rb) : kJagRows;
+    const int len = t < nr ? rp[i + 1] - rp[i] : -1;
+    slen[t] = len;
+    __syncthreads();
+    int rank = 0;
+    for (int u = 0; u < nr; ++u) {
+        const int lu = slen[u];
+        rank += (lu > len) || (lu == len && u < t);
+    }
+    const int t0 = bst[blockIdx.x], nsl = bst[blockIdx.x + 1] - t0;
+    for (int k = t; k < nsl; k += kJagRows) {
+        int sum = 0;
+        for (int u = 0; u < nr; ++u) sum += slen[u] < k ? slen[u] : k;
+        sst[k] = sum;
+        st[t0 + k] = sum;
+    }
+    __syncthreads();
+    if (t >= nr) return;
+    jrows[rb + rank] = (int32_t)i;
+    const int p0 = rp[rb], a = rp[i];
+    for (int k = 0; k < len; ++k) {
+        const int q = p0 + sst[k] + rank;
+        jci[q] = ci[a + k];
+        jv[q] = v[a + k];
     }
 }
 
@@ -358,11 +511,11 @@ __global__ void __launch_bounds__(256) k_lu_solve_wave(int n, const double *__re
 
 constexpr int BT = 256;
 
-template <typename T, int ROWS, int LDSN>
+template <typename T, int ROWS, int NT, int LDSN>
 static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
                      hipStream_t s) {
     const unsigned g = nblocks(A.nrows, ROWS);
-#define MGR_STREAM(M) k_csr_stream<T, M, ROWS, LDSN><<<g, ROWS, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2)
+#define MGR_STREAM(M) k_csr_stream<T, M, ROWS, NT, LDSN><<<g, NT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2)
     switch (mode) {
     case 0: MGR_STREAM(0); break;
     case 1: MGR_STREAM(1); break;
@@ -371,6 +524,34 @@ static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T
     default: MGR_STREAM(4); break;
     }
 #undef MGR_STREAM
+}
+
+template <typename T>
+static const T *jag_vals(const Jag &J);
+template <>
+const double *jag_vals<double>(const Jag &J) { return J.v; }
+template <>
+const float *jag_vals<float>(const Jag &J) { return J.vf; }
+
+template <typename T>
+static void jag_rows(int mode, const DCsr &A, const T *x, const T *r, const T *d, T *y, T *y2, hipStream_t s) {
+    const Jag &J = *A.jag;
+    // passes of 4864 FP64 entries (19 per thread): with the 2 KB slot table the
+    // workgroup takes 40 KB of LDS, four per CU (5120 would leave three: +5 %
+    // on the coarse-grid sweep); FP32 8192
+    constexpr int LDSN = sizeof(T) == 4 ? 8192 : 4864;
+    const unsigned g = (unsigned)J.nblk;
+#define MGR_JAG(M)                                                                                          \
+    k_jag_stream<T, M, LDSN><<<g, kJagRows, 0, s>>>(A.nrows, A.rp, J.ci, jag_vals<T>(J), J.rows, J.bst, J.st, x, \
+                                                    r, d, y, y2)
+    switch (mode) {
+    case 0: MGR_JAG(0); break;
+    case 1: MGR_JAG(1); break;
+    case 2: MGR_JAG(2); break;
+    case 3: MGR_JAG(3); break;
+    default: MGR_JAG(4); break;
+    }
+#undef MGR_JAG
 }
 
 template <typename T, int MODE>
@@ -406,10 +587,14 @@ static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T 
     if (A.nrows <= 0) return;
     const double avg = (double)A.nnz / (double)A.nrows;
     if (A.nrows >= kCsrStreamMinRows) {
-        if (avg < kStreamShortRow) csr_rows<T, 256, 1024>(mode, A, vals, x, r, d, y, y2, s);
-        else if (avg < kStreamMidRow) csr_rows<T, 256, 2048>(mode, A, vals, x, r, d, y, y2, s);
-        else if (sizeof(T) == 4) csr_rows<T, 256, 8192>(mode, A, vals, x, r, d, y, y2, s);
-        else csr_rows<T, 256, 5120>(mode, A, vals, x, r, d, y, y2, s);
+        if (A.jag && avg >= kStreamMidRow) {
+            jag_rows<T>(mode, A, x, r, d, y, y2, s);
+            return;
+        }
+        if (avg < kStreamShortRow) csr_rows<T, 256, 256, 1024>(mode, A, vals, x, r, d, y, y2, s);
+        else if (avg < kStreamMidRow) csr_rows<T, 256, 256, 2048>(mode, A, vals, x, r, d, y, y2, s);
+        else if (sizeof(T) == 4) csr_rows<T, 256, 256, 8192>(mode, A, vals, x, r, d, y, y2, s);
+        else csr_rows<T, 256, 256, 5120>(mode, A, vals, x, r, d, y, y2, s);
         return;
     }
     const int lanes = avg < 3 ? 2 : avg < 6 ? 4 : avg < 12 ? 8 : avg < 24 ? 16 : 32;
@@ -420,6 +605,19 @@ static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T 
     case 3: csr_lanes<T, 3>(A, lanes, vals, x, r, d, y, y2, s); break;
     default: csr_lanes<T, 4>(A, lanes, vals, x, r, d, y, y2, s); break;
     }
+}
+
+bool csr_long_rows(const DCsr &A) {
+    return A.nrows >= kCsrStreamMinRows && (double)A.nnz >= kStreamMidRow * (double)A.nrows;
+}
+
+void launch_jag_count(const DCsr &A, int32_t *cnt, hipStream_t s) {
+    const unsigned g = nblocks(A.nrows, kJagRows);
+    if (g) k_jag_count<<<g, kJagRows, 0, s>>>(A.nrows, A.rp, cnt);
+}
+
+void launch_jag_fill(const DCsr &A, Jag &J, hipStream_t s) {
+    if (J.nblk) k_jag_fill<<<(unsigned)J.nblk, kJagRows, 0, s>>>(A.nrows, A.rp, A.ci, A.v, J.bst, J.st, J.rows, J.ci, J.v);
 }
 
 template <typename T>

@@ -472,12 +472,39 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
 
 // Classical AMG hierarchy on Atop (kept as its level 0): strength -> PMIS ->
 // classical interpolation -> Galerkin P^T (A P), down to a dense LU.
+// The row-block jagged copy of a long-row level matrix for the solve-phase
+// SpMV (rows longer than kJagMaxSlots keep the CSR stream kernel).
+void build_jag(mgr_handle *h, AmgHier &H, DCsr &A) {
+    if (!csr_long_rows(A)) return;
+    reset_err(h);
+    launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
+    read_err(h);
+    if (h->herr[1] > kJagMaxSlots) return;
+    auto J = std::make_unique<Jag>();
+    J->nblk = (A.nrows + kJagRows - 1) / kJagRows;
+    {
+        ScratchScope scope(h);
+        Tmp<int32_t> cnt(h, J->nblk);
+        launch_jag_count(A, cnt.p, h->stream);
+        J->bst = dalloc<int32_t>(h, J->nblk + 1);
+        J->nst = scan(h, cnt.p, J->bst, J->nblk);
+    }
+    J->st = dalloc<int32_t>(h, J->nst);
+    J->rows = dalloc<int32_t>(h, A.nrows);
+    J->ci = dalloc<int32_t>(h, A.nnz);
+    J->v = dalloc<double>(h, A.nnz);
+    launch_jag_fill(A, *J, h->stream);
+    A.jag = J.get();
+    H.jags.push_back(std::move(J));
+}
+
 void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
     const mgr_options &o = h->o;
     H.pre = pre;
     H.post = post;
     DCsr A = Atop;
     for (int k = 0;; ++k) {
+        build_jag(h, H, A);
         H.lev.emplace_back();
         AmgLevel &lv = H.lev.back();
         lv.A = A;
@@ -606,6 +633,7 @@ void amg_to_mixed(mgr_handle *h, AmgHier &H) {
     for (size_t k = 0; k + 1 < H.lev.size(); ++k) {
         AmgLevel &lv = H.lev[k];
         lv.A.vf = to_f32(h, lv.A.v, lv.A.nnz);
+        if (lv.A.jag) lv.A.jag->vf = to_f32(h, lv.A.jag->v, lv.A.nnz);
         lv.P.vf = to_f32(h, lv.P.v, lv.P.nnz);
         lv.PT.vf = to_f32(h, lv.PT.v, lv.PT.nnz);
         lv.l1f = to_f32(h, lv.l1, lv.n);
@@ -689,7 +717,12 @@ inline void acct(mgr_handle *h, double bytes) {
 }
 
 double csr_bytes(const DCsr &A, int mode, double S) {
-    double b = (double)A.nnz * (S + 4.0) + 4.0 * (double)(A.nrows + 1) + S * (double)A.ncols + S * (double)A.nrows;
+    // row pointers, or for a jagged copy the rank-to-row map, the slot tables
+    // and two row pointers and two table offsets per block
+    const double index = A.jag && csr_long_rows(A)
+                             ? 4.0 * (double)A.nrows + 4.0 * (double)A.jag->nst + 16.0 * (double)A.jag->nblk
+                             : 4.0 * (double)(A.nrows + 1);
+    double b = (double)A.nnz * (S + 4.0) + index + S * (double)A.ncols + S * (double)A.nrows;
     if (mode == 1 || mode == 2) b += S * (double)A.nrows;
     if (mode == 3) b += 2.0 * S * (double)A.nrows;
     return b;

@@ -14,13 +14,34 @@ namespace mgr {
 
 constexpr int kWave = 64;
 
+// Solve-phase copy of a long-row CSR matrix in row-block jagged order: the
+// rows are taken in blocks of kJagRows; inside a block they are ranked by length
+// (longest first, ties by row), and the block's entries are stored slot by slot
+// (slot k holds the k-th entry of every row longer than k, in rank order), over
+// the same entry range [rp[block start], rp[block end]) as the CSR.  Entry k of
+// the row of rank s then sits at st[bst[b] + k] + s of its block, so a stream
+// of consecutive entries gathers x for consecutive rows at the same stencil slot.
+constexpr int kJagRows = 256;
+constexpr int kJagMaxSlots = 508;  // longest row a jagged copy takes (the slot table fits 2 KB of LDS)
+struct Jag {
+    int64_t nblk = 0, nst = 0;
+    int32_t *ci = nullptr;   // nnz, jagged order
+    double *v = nullptr;     // nnz, jagged order
+    float *vf = nullptr;
+    int32_t *rows = nullptr; // n: row of each rank (global row index)
+    int32_t *bst = nullptr;  // nblk + 1: start of each block's slot table in st
+    int32_t *st = nullptr;   // per block, maxlen + 1 slot starts relative to the block's first entry
+};
+
 // Device CSR (int32 row pointers and columns).  vf is the FP32 copy of the
-// values used by the mixed-precision hierarchy.
+// values used by the mixed-precision hierarchy.  jag: the solve-phase copy of a
+// long-row matrix (null when the matrix has none).
 struct DCsr {
     int64_t nrows = 0, ncols = 0, nnz = 0;
     int32_t *rp = nullptr, *ci = nullptr;
     double *v = nullptr;
     float *vf = nullptr;
+    Jag *jag = nullptr;
 };
 
 // Cell-sliced ELL of the level-0 operator: 64 consecutive cells form a slice;
@@ -51,6 +72,7 @@ struct AmgLevel {
 // one classical AMG hierarchy: the coarse-grid solver, or the F-block solver of an MGR level
 struct AmgHier {
     std::vector<AmgLevel> lev;
+    std::vector<std::unique_ptr<Jag>> jags;  // the jagged copies its level matrices point to
     int64_t ncoarse = 0;
     double *lu = nullptr;
     int32_t *perm = nullptr;
@@ -237,6 +259,13 @@ void launch_pattern_outer(int64_t n, const int32_t *rp, const int32_t *ci, const
 template <typename T>
 void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s);
 // mode 0: y = A x;  1: y = r - A x;  2: y += A x;  3: y = x + (r - A x) / d (x != y)
+// Whether the solve-phase kernels would stream A as a long-row matrix (the
+// matrices that get a jagged copy).
+bool csr_long_rows(const DCsr &A);
+// Jagged copy: per-block longest row (maxlen + 1 into cnt[b]), then, with the
+// exclusive scan of cnt in bst, the ranks, slot tables and the reordered entries.
+void launch_jag_count(const DCsr &A, int32_t *cnt, hipStream_t s);
+void launch_jag_fill(const DCsr &A, Jag &J, hipStream_t s);
 template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s);
 // y = A x and y2 = y / d (restriction that also starts the next level's Jacobi sweeps)
