@@ -569,18 +569,24 @@ static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const
 #undef MGR_LANES
 }
 
-// below this many rows the lanes-per-row kernel is faster (measured on the 128^3
-// hierarchy: stream everywhere costs 40 % more solve time, lanes on levels of up
-// to 600k rows about 1 % more)
+// Levels of at least kCsrStreamMinRows rows take 256-row stream workgroups (or
+// the jagged kernel); levels of kCsrStreamSmallRows up to that take the stream
+// kernel with row blocks sized so that a block's entries about fill one pass
+// (64 rows of >= 24 entries, 128 rows of >= 12), which issues a level's loads
+// in one wave of workgroups (AMG level 2 of the 128^3 coarse grid, 123 k rows of
+// 38 entries: 25 -> 17 us per sweep against the lanes kernel); smaller levels
+// take the lanes-per-row kernel, whose launches are latency-bound anyway.
 constexpr int64_t kCsrStreamMinRows = 131072;
+constexpr int64_t kCsrStreamSmallRows = 8192;
 // mean row lengths below which the stream kernel takes 1024- and 2048-entry passes
 // (above: 5120 entries in FP64, 20 per thread, 40 KB of LDS: 4 workgroups per CU;
 // 8192 in FP32)
 constexpr double kStreamShortRow = 3.0;
 constexpr double kStreamMidRow = 8.0;
 
-// Large levels: 256-row stream workgroups (sequential row sums).  Small levels,
-// where those would leave most CUs idle: several lanes per row.
+// Large levels: 256-row stream workgroups, or the jagged kernel where the matrix
+// has a jagged copy; mid-size levels: stream workgroups of fewer rows (all with
+// sequential row sums).  Small levels: several lanes per row.
 template <typename T>
 static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
                     hipStream_t s) {
@@ -595,6 +601,12 @@ static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T 
         else if (avg < kStreamMidRow) csr_rows<T, 256, 256, 2048>(mode, A, vals, x, r, d, y, y2, s);
         else if (sizeof(T) == 4) csr_rows<T, 256, 256, 8192>(mode, A, vals, x, r, d, y, y2, s);
         else csr_rows<T, 256, 256, 5120>(mode, A, vals, x, r, d, y, y2, s);
+        return;
+    }
+    if (A.nrows >= kCsrStreamSmallRows) {
+        if (avg >= 24) csr_rows<T, 64, 256, 4864>(mode, A, vals, x, r, d, y, y2, s);
+        else if (avg >= 12) csr_rows<T, 128, 256, 4864>(mode, A, vals, x, r, d, y, y2, s);
+        else csr_rows<T, 256, 256, 2048>(mode, A, vals, x, r, d, y, y2, s);
         return;
     }
     const int lanes = avg < 3 ? 2 : avg < 6 ? 4 : avg < 12 ? 8 : avg < 24 ? 16 : 32;

@@ -46,8 +46,9 @@ def test_vcycle_matches_oracle(orc, precision, opts):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_vcycle_with_stream_amg_levels_matches_oracle(orc, precision):
     # 52^3 cells: the coarse-grid matrix has 140,608 rows of ~23 entries, so its
-    # sweeps and residuals run in the 256-row stream kernel with 4096-entry passes
-    # (the V-cycle tests above only reach the small-level kernels)
+    # sweeps and residuals run in the jagged stream kernel over its row-block
+    # jagged copy, and the next AMG levels in the stream kernel with 64- and
+    # 128-row blocks (the V-cycle tests above only reach the small-level kernels)
     s = small_system((52, 52, 52), seed=6, sigma=2.0, frac=0.3, region="ball")
     print(f"[vcycle stream levels] n={s.n} {precision}", flush=True)
     o = orc.Oracle(oracle_csr(orc, s), s.labels, precision=1 if precision == "mixed" else 0, frelax_amg_mask=2)
