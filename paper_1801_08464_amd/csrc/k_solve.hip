@@ -507,6 +507,181 @@ __global__ void __launch_bounds__(256) k_lu_solve_wave(int n, const double *__re
     if (l < n) x[l] = (T)y;
 }
 
+// ---- the bottom of an AMG V-cycle in one workgroup ----
+// out(i, (A x)_i) for every row i of a tail-level matrix held in LDS against a
+// vector in LDS, with all threads of the workgroup: L lanes per row (the
+// largest power of two up to 32 with L * rows <= threads), each summing a
+// strided share of the row, then a fixed xor-tree across its lanes (the lanes
+// kernel's order).  Consecutive lanes read consecutive words of a row, which
+// keeps the LDS reads free of bank conflicts.
+template <typename T, typename F>
+__device__ inline void tail_spmv(int nrows, const int32_t *rp, const int32_t *ci, const T *v, const T *xl, F out) {
+    int L = 1;
+    while (L < 32 && 2 * L * nrows <= kTailThreads) L *= 2;
+    for (int base = 0; base < nrows * L; base += kTailThreads) {
+        const int g = base + (int)threadIdx.x;
+        const int row = g / L, sub = g % L;
+        T acc = 0;
+        if (row < nrows) {
+            const int e = rp[row + 1];
+            for (int p = rp[row] + sub; p < e; p += L) {
+                const T pr = v[p] * xl[ci[p]];
+                acc = acc + pr;
+            }
+        }
+        for (int o = L / 2; o > 0; o >>= 1) acc = acc + __shfl_xor(acc, o);
+        if (row < nrows && sub == 0) out(row, acc);
+    }
+}
+
+// LDS offset (in T, from the start of the vectors) of tail level k's vectors
+// r, xa, xb, t (k == nlev: the coarsest level's r and x)
+template <typename T>
+__device__ inline int tail_off(const TailDesc<T> &d, int k) {
+    int o = 0;
+    for (int j = 0; j < k; ++j) o += 4 * d.n[j];
+    return o;
+}
+
+// The V-cycle of amg_cycle from level k0 down to the dense coarsest level and
+// back, in one workgroup: the same steps and roundings (Jacobi iterate from
+// zero r / l1, pre - 1 more l1-Jacobi sweeps, residual, restriction with the
+// next level's first iterate, LU solve, prolongation, post sweeps).  The
+// levels' matrices, l1 and the LU factors are first copied into LDS from their
+// packed device copy, 16 bytes per load and eight loads per thread in flight;
+// the work vectors live in LDS too, several lanes per row.
+// A level's iterate ping-pongs between xa and xb; which one is final follows
+// from the number of sweeps.
+template <typename T>
+__global__ void __launch_bounds__(kTailThreads) k_amg_tail(const TailDesc<T> d) {
+    __shared__ __align__(16) unsigned char lds[kTailLdsBytes];
+    const int tid = threadIdx.x;
+    {
+        uint4 *dst = reinterpret_cast<uint4 *>(lds);
+        for (int q0 = 0; q0 < d.pack16; q0 += 8 * kTailThreads) {
+            uint4 b0, b1, b2, b3, b4, b5, b6, b7;
+            const int q = q0 + tid;
+            const int last = d.pack16 - 1;
+            // every load in bounds (clamped), the stores guarded
+            b0 = d.pack[min(q, last)];
+            b1 = d.pack[min(q + kTailThreads, last)];
+            b2 = d.pack[min(q + 2 * kTailThreads, last)];
+            b3 = d.pack[min(q + 3 * kTailThreads, last)];
+            b4 = d.pack[min(q + 4 * kTailThreads, last)];
+            b5 = d.pack[min(q + 5 * kTailThreads, last)];
+            b6 = d.pack[min(q + 6 * kTailThreads, last)];
+            b7 = d.pack[min(q + 7 * kTailThreads, last)];
+            if (q < d.pack16) dst[q] = b0;
+            if (q + kTailThreads < d.pack16) dst[q + kTailThreads] = b1;
+            if (q + 2 * kTailThreads < d.pack16) dst[q + 2 * kTailThreads] = b2;
+            if (q + 3 * kTailThreads < d.pack16) dst[q + 3 * kTailThreads] = b3;
+            if (q + 4 * kTailThreads < d.pack16) dst[q + 4 * kTailThreads] = b4;
+            if (q + 5 * kTailThreads < d.pack16) dst[q + 5 * kTailThreads] = b5;
+            if (q + 6 * kTailThreads < d.pack16) dst[q + 6 * kTailThreads] = b6;
+            if (q + 7 * kTailThreads < d.pack16) dst[q + 7 * kTailThreads] = b7;
+        }
+    }
+    auto I = [&](int off) { return reinterpret_cast<const int32_t *>(lds + off); };
+    auto V = [&](int off) { return reinterpret_cast<const T *>(lds + off); };
+    T *vec = reinterpret_cast<T *>(lds + d.vec);
+    const int K = d.nlev, nc = d.nc;
+    {
+        const int n = d.n[0];
+        T *r = vec, *xa = vec + n;
+        for (int i = tid; i < n; i += kTailThreads) {
+            r[i] = d.r_in[i];
+            if (d.x0_ready) xa[i] = d.x0_in[i];
+        }
+    }
+    __syncthreads();
+    const int sw_pre = d.pre > 0 ? d.pre - 1 : 0;
+    // down
+    for (int k = 0; k < K; ++k) {
+        const int n = d.n[k];
+        const int32_t *arp = I(d.arp[k]), *aci = I(d.aci[k]);
+        const T *av = V(d.av[k]), *l1 = V(d.l1[k]);
+        T *r = vec + tail_off(d, k), *xa = r + n, *xb = xa + n, *t = xb + n;
+        T *cur = xa, *oth = xb;
+        if (d.pre > 0) {
+            const bool have_x0 = k == 0 ? d.x0_ready != 0 : true;
+            if (!have_x0) {
+                for (int i = tid; i < n; i += kTailThreads) xa[i] = r[i] / l1[i];
+                __syncthreads();
+            }
+            for (int it = 1; it < d.pre; ++it) {
+                T *c = cur, *o = oth;
+                tail_spmv(n, arp, aci, av, c, [&](int i, T acc) { o[i] = c[i] + (r[i] - acc) / l1[i]; });
+                __syncthreads();
+                cur = o;
+                oth = c;
+            }
+        } else {
+            for (int i = tid; i < n; i += kTailThreads) xa[i] = (T)0;
+            __syncthreads();
+        }
+        {
+            T *c = cur;
+            tail_spmv(n, arp, aci, av, c, [&](int i, T acc) { t[i] = r[i] - acc; });
+        }
+        __syncthreads();
+        const bool next_coarse = k + 1 == K;
+        const int nn = next_coarse ? nc : d.n[k + 1];
+        T *rn = vec + tail_off(d, k + 1);
+        const T *l1n = next_coarse ? nullptr : V(d.l1[k + 1]);
+        const bool div = d.pre > 0 && !next_coarse;
+        tail_spmv(nn, I(d.rrp[k]), I(d.rci[k]), V(d.rv[k]), t, [&](int j, T acc) {
+            rn[j] = acc;
+            if (div) rn[nn + j] = acc / l1n[j];
+        });
+        __syncthreads();
+    }
+    // coarsest: the substitutions of k_lu_solve_wave in the first wavefront
+    {
+        const double *LU = reinterpret_cast<const double *>(lds + d.lu);
+        const int32_t *perm = I(d.perm);
+        T *rK = vec + tail_off(d, K), *xK = rK + nc;
+        if (tid < kWave) {
+            const int l = tid;
+            double y = l < nc ? (double)rK[perm[l]] : 0.0;
+            for (int k = 0; k < nc; ++k) {
+                const double yk = lane_bcast(y, k);
+                if (l > k && l < nc) y = y - LU[l * nc + k] * yk;
+            }
+            for (int k = nc - 1; k >= 0; --k) {
+                if (l == k) y = y / LU[k * nc + k];
+                const double yk = lane_bcast(y, k);
+                if (l < k) y = y - LU[l * nc + k] * yk;
+            }
+            if (l < nc) xK[l] = (T)y;
+        }
+        __syncthreads();
+    }
+    // up
+    const T *xnext = vec + tail_off(d, K) + nc;
+    for (int k = K - 1; k >= 0; --k) {
+        const int n = d.n[k];
+        const int32_t *arp = I(d.arp[k]), *aci = I(d.aci[k]);
+        const T *av = V(d.av[k]), *l1 = V(d.l1[k]);
+        T *r = vec + tail_off(d, k), *xa = r + n, *xb = xa + n;
+        T *cur = (sw_pre % 2 == 0) ? xa : xb;
+        T *oth = (cur == xa) ? xb : xa;
+        {
+            T *c = cur;
+            tail_spmv(n, I(d.prp[k]), I(d.pci[k]), V(d.pv[k]), xnext, [&](int i, T acc) { c[i] = c[i] + acc; });
+        }
+        __syncthreads();
+        for (int it = 0; it < d.post; ++it) {
+            T *c = cur, *o = oth;
+            tail_spmv(n, arp, aci, av, c, [&](int i, T acc) { o[i] = c[i] + (r[i] - acc) / l1[i]; });
+            __syncthreads();
+            cur = o;
+            oth = c;
+        }
+        xnext = cur;
+    }
+    for (int i = tid; i < d.n[0]; i += kTailThreads) d.x_out[i] = xnext[i];
+}
+
 }  // namespace
 
 constexpr int BT = 256;
@@ -633,6 +808,11 @@ void launch_jag_fill(const DCsr &A, Jag &J, hipStream_t s) {
 }
 
 template <typename T>
+void launch_amg_tail(const TailDesc<T> &d, hipStream_t s) {
+    k_amg_tail<T><<<1, kTailThreads, 0, s>>>(d);
+}
+
+template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
     csr_any<T>(mode, A, vals, x, r, d, y, nullptr, s);
 }
@@ -730,6 +910,7 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
 }
 
 #define MGR_INSTANTIATE(T)                                                                                      \
+    template void launch_amg_tail<T>(const TailDesc<T> &, hipStream_t);                                       \
     template void launch_csr<T>(int, const DCsr &, const T *, const T *, const T *, const T *, T *, hipStream_t); \
     template void launch_csr_restrict_div<T>(const DCsr &, const T *, const T *, const T *, T *, T *, hipStream_t); \
     template void launch_csr_rows_residual<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *, \

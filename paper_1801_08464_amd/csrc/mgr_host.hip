@@ -498,6 +498,98 @@ void build_jag(mgr_handle *h, AmgHier &H, DCsr &A) {
     H.jags.push_back(std::move(J));
 }
 
+// The levels the single-workgroup tail kernel takes (the longest run of levels
+// above the coarsest with at most kTailMaxRows rows whose matrices, l1 norms,
+// LU factors and work vectors fit its LDS; the coarsest level a dense solve of
+// at most 64 rows), and their packed copy in the kernel's LDS layout: first the
+// index arrays (A, P, P^T row pointers and columns of each level, the LU
+// permutation), then the values (A, P, P^T, l1 of each level, in the
+// hierarchy's precision), then the LU factors.  Built after the FP32 copies.
+void build_tail(mgr_handle *h, AmgHier &H) {
+    H.tail = -1;
+    H.tail_pack = nullptr;
+    H.tail_pack_bytes = 0;
+    const int K = (int)H.lev.size() - 1;
+    if (K < 1 || H.ncoarse < 1 || H.ncoarse > kWave) return;
+    const int64_t S = h->o.precision == 1 ? 4 : 8;
+    const int64_t nc = H.ncoarse;
+    auto a16 = [](int64_t b) { return (b + 15) / 16 * 16; };
+    // LDS bytes of the tail starting at level k0
+    auto bytes = [&](int k0) {
+        int64_t ib = 4 * nc, vb = 0, vec = 2 * nc;
+        for (int j = k0; j < K; ++j) {
+            const AmgLevel &lv = H.lev[j];
+            ib += 4 * (lv.n + 1 + lv.A.nnz) + 4 * (lv.n + 1 + lv.P.nnz) + 4 * (lv.PT.nrows + 1 + lv.PT.nnz);
+            vb += S * (lv.A.nnz + lv.P.nnz + lv.PT.nnz + lv.n);
+            vec += 4 * lv.n;
+        }
+        return a16(ib) + a16(vb) + a16(8 * nc * nc) + vec * S;
+    };
+    int k0 = K;
+    while (k0 > 0 && K - (k0 - 1) <= kTailMaxLevels && H.lev[k0 - 1].n <= kTailMaxRows &&
+           bytes(k0 - 1) <= kTailLdsBytes)
+        --k0;
+    if (k0 == K) return;
+    // offsets
+    int64_t o = 0;
+    for (int j = k0; j < K; ++j) {
+        const AmgLevel &lv = H.lev[j];
+        AmgHier::TailOffsets &t = H.tail_off[j - k0];
+        t.arp = (int)o; o += 4 * (lv.n + 1);
+        t.aci = (int)o; o += 4 * lv.A.nnz;
+        t.prp = (int)o; o += 4 * (lv.n + 1);
+        t.pci = (int)o; o += 4 * lv.P.nnz;
+        t.rrp = (int)o; o += 4 * (lv.PT.nrows + 1);
+        t.rci = (int)o; o += 4 * lv.PT.nnz;
+    }
+    H.tail_perm = (int)o;
+    o = a16(o + 4 * nc);
+    for (int j = k0; j < K; ++j) {
+        const AmgLevel &lv = H.lev[j];
+        AmgHier::TailOffsets &t = H.tail_off[j - k0];
+        t.av = (int)o; o += S * lv.A.nnz;
+        t.pv = (int)o; o += S * lv.P.nnz;
+        t.rv = (int)o; o += S * lv.PT.nnz;
+        t.l1 = (int)o; o += S * lv.n;
+    }
+    o = a16(o);
+    H.tail_lu = (int)o;
+    o = a16(o + 8 * nc * nc);
+    H.tail_pack_bytes = o;
+    H.tail_pack = dalloc<unsigned char>(h, o);
+    unsigned char *P = H.tail_pack;
+    hipStream_t s = h->stream;
+    auto put = [&](int off, const void *src, int64_t b) {
+        if (b > 0) HIPCHK(hipMemcpyAsync(P + off, src, b, hipMemcpyDeviceToDevice, s));
+    };
+    const bool f32 = S == 4;
+    for (int j = k0; j < K; ++j) {
+        const AmgLevel &lv = H.lev[j];
+        const AmgHier::TailOffsets &t = H.tail_off[j - k0];
+        put(t.arp, lv.A.rp, 4 * (lv.n + 1));
+        put(t.aci, lv.A.ci, 4 * lv.A.nnz);
+        put(t.prp, lv.P.rp, 4 * (lv.n + 1));
+        put(t.pci, lv.P.ci, 4 * lv.P.nnz);
+        put(t.rrp, lv.PT.rp, 4 * (lv.PT.nrows + 1));
+        put(t.rci, lv.PT.ci, 4 * lv.PT.nnz);
+        put(t.av, f32 ? (const void *)lv.A.vf : (const void *)lv.A.v, S * lv.A.nnz);
+        put(t.pv, f32 ? (const void *)lv.P.vf : (const void *)lv.P.v, S * lv.P.nnz);
+        put(t.rv, f32 ? (const void *)lv.PT.vf : (const void *)lv.PT.v, S * lv.PT.nnz);
+        put(t.l1, f32 ? (const void *)lv.l1f : (const void *)lv.l1, S * lv.n);
+    }
+    put(H.tail_perm, H.perm, 4 * nc);
+    put(H.tail_lu, H.lu, 8 * nc * nc);
+    H.tail = k0;
+}
+
+// the tails of the coarse-grid hierarchy and of every F-block hierarchy
+void build_tails(mgr_handle *h) {
+    AmgArenaScope amg_arena(h);
+    build_tail(h, h->cg);
+    for (auto &lv : h->lev)
+        if (lv.ff) build_tail(h, *lv.ff);
+}
+
 void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
     const mgr_options &o = h->o;
     H.pre = pre;
@@ -785,6 +877,44 @@ bool amg_takes_x0(const AmgHier &H) {
 
 // x0_ready: the caller's restriction already wrote x0 = r / l1 (the first Jacobi
 // iterate from zero) where this level's first sweep reads it
+// Levels k.. of H in one launch of the tail kernel (same steps and roundings as
+// the recursion below).  Bytes: what the kernel reads and writes in memory (its
+// packed matrices, l1 and LU factors once, r, x0 and x of level k).
+template <typename T>
+void tail_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready) {
+    const int K = (int)H.lev.size() - 1;
+    TailDesc<T> d;
+    d.nlev = K - k;
+    d.pre = H.pre;
+    d.post = H.post;
+    d.x0_ready = x0_ready ? 1 : 0;
+    d.nc = (int)H.ncoarse;
+    d.pack16 = (int)(H.tail_pack_bytes / 16);
+    d.lu = H.tail_lu;
+    d.perm = H.tail_perm;
+    d.vec = (int)H.tail_pack_bytes;
+    d.pack = reinterpret_cast<const uint4 *>(H.tail_pack);
+    d.r_in = r;
+    d.x0_in = x0_ready ? amg_x0_buffer<T>(H, k, x) : nullptr;
+    d.x_out = x;
+    for (int j = 0; j < d.nlev; ++j) {
+        const AmgHier::TailOffsets &t = H.tail_off[j];
+        d.n[j] = (int)H.lev[k + j].n;
+        d.arp[j] = t.arp;
+        d.aci[j] = t.aci;
+        d.av[j] = t.av;
+        d.prp[j] = t.prp;
+        d.pci[j] = t.pci;
+        d.pv[j] = t.pv;
+        d.rrp[j] = t.rrp;
+        d.rci[j] = t.rci;
+        d.rv[j] = t.rv;
+        d.l1[j] = t.l1;
+    }
+    launch_amg_tail<T>(d, h->stream);
+    acct(h, (double)H.tail_pack_bytes + (double)sizeof(T) * (double)d.n[0] * (x0_ready ? 3.0 : 2.0));
+}
+
 template <typename T>
 void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready = false) {
     AmgLevel &lv = H.lev[k];
@@ -794,6 +924,10 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready
     if (k == (int)H.lev.size() - 1) {
         launch_lu_solve<T>(n, H.lu, H.perm, r, x, s);
         acct(h, 8.0 * n * n + 4.0 * n + 2.0 * S * n);
+        return;
+    }
+    if (k == H.tail) {
+        tail_cycle<T>(h, H, k, r, x, x0_ready);
         return;
     }
     const T *Av = P_<T>::v(lv.A);
@@ -1247,6 +1381,7 @@ void update_impl(mgr_handle *h, const double *values) {
     }
     if (h->o.precision == 1) to_mixed(h, true);
     alloc_work(h, true);
+    build_tails(h);
     arena_release(h, h->scratch);
     sync(h);
     h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1341,6 +1476,7 @@ int setup_impl(const mgr_csr *Ain, int bs, const int32_t *labels, const mgr_opti
         }
         if (h->o.precision == 1) to_mixed(h);
         alloc_work(h);
+        build_tails(h);
         const int m = h->m;
         h->ld = krylov_ld(n);
         h->V = dalloc<double>(h, (int64_t)(m + 1) * h->ld);

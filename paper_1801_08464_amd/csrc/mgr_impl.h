@@ -69,6 +69,12 @@ struct AmgLevel {
     float *rf = nullptr, *xf = nullptr, *x2f = nullptr, *tf = nullptr;
 };
 
+// Limits of the single-workgroup tail cycle (k_amg_tail, below).
+constexpr int kTailThreads = 1024;
+constexpr int kTailMaxLevels = 8;
+constexpr int kTailMaxRows = 1024;
+constexpr int kTailLdsBytes = 144 * 1024;
+
 // one classical AMG hierarchy: the coarse-grid solver, or the F-block solver of an MGR level
 struct AmgHier {
     std::vector<AmgLevel> lev;
@@ -77,6 +83,40 @@ struct AmgHier {
     double *lu = nullptr;
     int32_t *perm = nullptr;
     int pre = 2, post = 2;
+    int tail = -1;  // first level of the single-workgroup tail cycle (-1: none)
+    // the tail's matrices (A, P, P^T per level, with l1), the coarsest LU
+    // factors and permutation, packed in the LDS layout of the tail kernel
+    unsigned char *tail_pack = nullptr;
+    int64_t tail_pack_bytes = 0;
+    struct TailOffsets {
+        int arp, aci, av, prp, pci, pv, rrp, rci, rv, l1;
+    } tail_off[kTailMaxLevels];
+    int tail_lu = 0, tail_perm = 0;
+};
+
+// The bottom of an AMG V-cycle in one workgroup (k_amg_tail): levels of at most
+// kTailMaxRows rows down to a dense coarsest level of at most 64 rows.  The
+// matrices of those levels, their l1 norms and the coarsest LU factors are
+// copied into LDS in one coalesced pass (from a device buffer in the same
+// layout, built at setup), every work vector lives in LDS, and all products of
+// the cycle then read LDS only.
+template <typename T>
+struct TailDesc {
+    int nlev = 0;      // smoothing levels of the tail
+    int pre = 0, post = 0;
+    int x0_ready = 0;  // x0_in holds the first level's first Jacobi iterate r / l1
+    int nc = 0;        // rows of the coarsest level
+    int pack16 = 0;    // pack length in 16-byte words
+    int lu = 0, perm = 0, vec = 0;  // byte offsets in LDS
+    const uint4 *pack = nullptr;
+    const T *r_in = nullptr, *x0_in = nullptr;
+    T *x_out = nullptr;
+    int n[kTailMaxLevels] = {};
+    // byte offsets in LDS of each level's A, P (n rows), P^T (rows of the next level) and l1
+    int arp[kTailMaxLevels] = {}, aci[kTailMaxLevels] = {}, av[kTailMaxLevels] = {};
+    int prp[kTailMaxLevels] = {}, pci[kTailMaxLevels] = {}, pv[kTailMaxLevels] = {};
+    int rrp[kTailMaxLevels] = {}, rci[kTailMaxLevels] = {}, rv[kTailMaxLevels] = {};
+    int l1[kTailMaxLevels] = {};
 };
 
 struct MgrLevel {
@@ -302,6 +342,8 @@ template <typename T>
 void launch_scatter_set(int64_t n, const int32_t *map, const T *d, T *e, hipStream_t s);
 template <typename T>
 void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *b, T *x, hipStream_t s);
+template <typename T>
+void launch_amg_tail(const TailDesc<T> &d, hipStream_t s);
 
 // ---- semi-smooth Newton support (k_ncp.hip) ----
 void launch_axpy_inplace(int64_t n, double alpha, const double *du, double *u, hipStream_t s);

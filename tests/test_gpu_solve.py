@@ -255,8 +255,11 @@ def test_amg_frelaxation_solve_matched_iterations(orc):
 
 
 def test_kernel_timing_counts_and_bytes():
-    # kernel 0: every level-0 sliced-ELL launch; kernel 1: every preconditioner application
-    s = make_config(1)
+    # kernel 0: every level-0 sliced-ELL launch; kernel 1: every preconditioner
+    # application; kernel 2: the sweeps on the coarse-grid matrix, launched on
+    # their own when it is larger than the single-workgroup tail takes (1,600
+    # rows here; the levels below it run in the tail kernel)
+    s = small_system((40, 40), seed=5, sigma=1.0, frac=0.4)
     g = gpu_solver(s)
     g.set_kernel_timing(True)
     x, info = g.solve(s.b, 1e-8)
