@@ -139,8 +139,12 @@ int mgr_update_values(mgr_handle *h, const double *values);
 
 /*
  * Solve A x = b (or A^T x = b for a transpose handle) to
- * ||b - A x|| <= tol ||b|| with restarted right-preconditioned GMRES(m)
- * (Saad and Schultz 1986; the preconditioned directions are kept, x += Z y).
+ * ||b - A x|| <= tol ||b|| with restarted GMRES(m) right-preconditioned by the
+ * MGR V-cycle: the linear solve of each semi-smooth Newton step (Section 3.1),
+ * with the tolerance relative to the right-hand side and the iteration cap of
+ * the experiments of Section 6 (the paper uses the simulator's GMRES, the method
+ * its introduction cites; here the preconditioned directions are kept, x += Z y,
+ * which also serves the mixed-precision form as flexible GMRES).
  * b: device double[n] (read only).  x: device double[n] (output; also the
  * initial guess when use_x0).  stats may be NULL.
  * Returns MGR_OK, MGR_NOT_CONVERGED or MGR_E_BREAKDOWN.  ||b|| = 0 gives x = 0.
@@ -148,8 +152,9 @@ int mgr_update_values(mgr_handle *h, const double *values);
 int mgr_solve(mgr_handle *h, const double *b, double *x, double tol, mgr_stats *stats);
 
 /*
- * Gradient of a loss L(x), x = A^{-1} b, with respect to the stored values of
- * the matrix given to mgr_setup: dvals[k] = -lambda[row(k)] * x[col(k)] for
+ * Gradient of a loss L(x), x = A^{-1} b (the linear system of Section 3.2), with
+ * respect to the stored values of the matrix given to mgr_setup (the adjoint
+ * form of the solve): dvals[k] = -lambda[row(k)] * x[col(k)] for
  * each stored entry k, where lambda = A^{-T} dL/dx (from a transpose handle).
  * lambda, x: device double[n]; dvals: device double[nnz].  The pattern is the
  * one passed to mgr_setup of this handle (before any transposition).
