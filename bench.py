@@ -430,7 +430,7 @@ def main():
     cs = main_form.get("coarse_sweep")
     # the dominant kernel of a step: the l1-Jacobi sweep on the coarse-grid matrix
     # (three launches per iteration); the fine-level operator is reported beside it
-    roof = roofline(cs, "k_jag_stream<double, 3, 4864>: l1-Jacobi sweep on the coarse-grid matrix "
+    roof = roofline(cs, "k_jag_stream<double, int, 3, 4864>: l1-Jacobi sweep on the coarse-grid matrix "
                         "(AMG level 0 of the pressure system, row-block jagged copy)", SWEEP_RECORD, SWEEP_SOURCE,
                     args.config) if cs else None
     roof_fine = roofline(fk, "k_csell: level-0 sliced-ELL SpMV / residual (the GMRES operator)", FINE_RECORD,

@@ -147,18 +147,26 @@ __global__ void __launch_bounds__(NT) k_csr_stream(int64_t nrows, const int32_t 
 // those of the CSR stream kernel, bit for bit.  The block's slot table sits in
 // LDS; a row's entry k is at st[k] + s, so the owner threads read consecutive
 // LDS words.
-template <typename T, int MODE, int LDSN>
+//
+// IX = uint16_t: the columns are 16-bit offsets from their slot's base sb[k].
+// A thread's entries lie NT apart and a slot holds at most NT entries, so each
+// entry's slot is past the previous one's: the thread walks the slot table
+// forward, and over the block's full slots (NT entries each, the first `full`
+// ones) the slot is the entry's index / NT.
+template <typename T, typename IX, int MODE, int LDSN>
 __global__ void __launch_bounds__(kJagRows) k_jag_stream(int64_t nrows, const int32_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ jci, const T *__restrict__ jv,
-                                                         const int32_t *__restrict__ jrows,
+                                                         const IX *__restrict__ jci, const int32_t *__restrict__ sb,
+                                                         const T *__restrict__ jv, const int32_t *__restrict__ jrows,
                                                          const int32_t *__restrict__ bst,
                                                          const int32_t *__restrict__ st, const T *__restrict__ x,
                                                          const T *__restrict__ r, const T *__restrict__ d,
                                                          T *__restrict__ y, T *__restrict__ y2) {
     constexpr int NT = kJagRows;
     constexpr int B = LDSN / NT;
+    constexpr bool kOff = sizeof(IX) == 2;
     __shared__ T sh[LDSN];
     __shared__ int sst[kJagMaxSlots + 1];
+    __shared__ int ssb[kOff ? kJagMaxSlots + 1 : 1];
     const int tid = threadIdx.x;
     const int64_t blk = xcd_grouped_block<kXcdGroupRows / kJagRows>();
     const int64_t rb = blk * NT;
@@ -166,21 +174,27 @@ __global__ void __launch_bounds__(kJagRows) k_jag_stream(int64_t nrows, const in
     const int p0 = rp[rb];
     const int total = rp[re] - p0;
     const int t0 = bst[blk], nsl = bst[blk + 1] - t0;  // maxlen + 1 slot starts
-    for (int k = tid; k < nsl; k += NT) sst[k] = st[t0 + k];
+    for (int k = tid; k < nsl; k += NT) {
+        sst[k] = st[t0 + k];
+        if (kOff) ssb[k] = sb[t0 + k];
+    }
     const bool owner = rb + tid < re;
     const int64_t row = owner ? jrows[rb + tid] : 0;
     __syncthreads();
-    // the owner's row length: the number of slots holding more than tid rows
-    int len = 0;
-    if (owner) {
-        int lo = 0, hi = nsl - 1;  // slots [0, hi) all have count > tid iff ...
+    // the number of leading slots holding more than t rows (= the row length of
+    // rank t)
+    auto slots_over = [&](int t) {
+        int lo = 0, hi = nsl - 1;
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (sst[mid + 1] - sst[mid] > tid) lo = mid + 1;
+            if (sst[mid + 1] - sst[mid] > t) lo = mid + 1;
             else hi = mid;
         }
-        len = lo;
-    }
+        return lo;
+    };
+    const int len = owner ? slots_over(tid) : 0;
+    const int full_end = kOff ? slots_over(NT - 1) * NT : 0;
+    int ks = -1;  // slot of this thread's previous entry
     constexpr bool kEarlyRowIn = sizeof(T) == 4;
     RowIn<T, MODE> in;
     if (owner && kEarlyRowIn) in.load(row, x, r, d, y);
@@ -193,8 +207,33 @@ __global__ void __launch_bounds__(kJagRows) k_jag_stream(int64_t nrows, const in
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const int q = w0 + u * NT + tid;
-            j[u] = q < w1 ? __builtin_nontemporal_load(jci + p0 + q) : -1;
+            j[u] = q < w1 ? (int)__builtin_nontemporal_load(jci + p0 + q) : -1;
             av[u] = q < w1 ? __builtin_nontemporal_load(jv + p0 + q) : (T)0;
+        }
+        if (kOff) {
+            // the slots' bases first (LDS only: they overlap the loads in flight),
+            // then the columns
+            int base[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int q = w0 + u * NT + tid;
+                base[u] = 0;
+                if (q < w1) {
+                    int k;
+                    if (q < full_end) {
+                        k = q / NT;
+                    } else {
+                        // q < total = sst[nsl - 1] stops the walk at a slot
+                        k = ks + 1 > full_end / NT ? ks + 1 : full_end / NT;
+                        while (sst[k + 1] <= q) ++k;
+                    }
+                    ks = k;
+                    base[u] = ssb[k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (j[u] >= 0) j[u] += base[u];
         }
         T xv[B];
 #pragma unroll
@@ -251,14 +290,19 @@ __global__ void __launch_bounds__(kJagRows) k_jag_count(int64_t nrows, const int
 
 // Jagged copy, second pass (bst = exclusive scan of the counts): ranks (longer
 // rows first, ties by row), slot tables st[k] = sum over the block's rows of
-// min(len, k), and the entries in slot order.
+// min(len, k), and the entries in slot order.  With jco (the 16-bit form) each
+// slot's smallest column goes to sb[k] (parallel to st) and each entry's column
+// as its offset from it; an offset beyond 65535 sets *bad (the copy is then
+// unusable and the caller builds the 32-bit form).
 __global__ void __launch_bounds__(kJagRows) k_jag_fill(int64_t nrows, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci, const double *__restrict__ v,
                                                        const int32_t *__restrict__ bst, int32_t *__restrict__ st,
                                                        int32_t *__restrict__ jrows, int32_t *__restrict__ jci,
-                                                       double *__restrict__ jv) {
+                                                       uint16_t *__restrict__ jco, int32_t *__restrict__ sb,
+                                                       double *__restrict__ jv, int *__restrict__ bad) {
     __shared__ int slen[kJagRows];
     __shared__ int sst[kJagMaxSlots + 1];
+    __shared__ int smin[kJagMaxSlots + 1];
     const int t = threadIdx.x;
     const int64_t rb = (int64_t)blockIdx.x * kJagRows, i = rb + t;
     const int nr = nrows - rb < kJagRows ? (int)(nrows - rb) : kJagRows;
@@ -276,14 +320,28 @@ __global__ void __launch_bounds__(kJagRows) k_jag_fill(int64_t nrows, const int3
         for (int u = 0; u < nr; ++u) sum += slen[u] < k ? slen[u] : k;
         sst[k] = sum;
         st[t0 + k] = sum;
+        smin[k] = INT_MAX;
     }
     __syncthreads();
+    const int p0 = rp[rb], a = t < nr ? rp[i] : 0;
+    if (jco) {
+        for (int k = 0; k < len; ++k) atomicMin(&smin[k], ci[a + k]);
+        __syncthreads();
+        // the last table entry (the block's total) has no slot: base 0
+        for (int k = t; k < nsl; k += kJagRows) sb[t0 + k] = k + 1 < nsl ? smin[k] : 0;
+    }
     if (t >= nr) return;
     jrows[rb + rank] = (int32_t)i;
-    const int p0 = rp[rb], a = rp[i];
     for (int k = 0; k < len; ++k) {
         const int q = p0 + sst[k] + rank;
-        jci[q] = ci[a + k];
+        const int c = ci[a + k];
+        if (jco) {
+            const unsigned off = (unsigned)(c - smin[k]);
+            if (off > 0xffffu) *bad = 1;
+            jco[q] = (uint16_t)off;
+        } else {
+            jci[q] = c;
+        }
         jv[q] = v[a + k];
     }
 }
@@ -711,21 +769,29 @@ const float *jag_vals<float>(const Jag &J) { return J.vf; }
 template <typename T>
 static void jag_rows(int mode, const DCsr &A, const T *x, const T *r, const T *d, T *y, T *y2, hipStream_t s) {
     const Jag &J = *A.jag;
+    const unsigned g = (unsigned)J.nblk;
     // passes of 4864 FP64 entries (19 per thread): with the 2 KB slot table the
     // workgroup takes 40 KB of LDS, four per CU (5120 would leave three: +5 %
-    // on the coarse-grid sweep); FP32 8192
-    constexpr int LDSN = sizeof(T) == 4 ? 8192 : 4864;
-    const unsigned g = (unsigned)J.nblk;
-#define MGR_JAG(M)                                                                                          \
-    k_jag_stream<T, M, LDSN><<<g, kJagRows, 0, s>>>(A.nrows, A.rp, J.ci, jag_vals<T>(J), J.rows, J.bst, J.st, x, \
-                                                    r, d, y, y2)
-    switch (mode) {
-    case 0: MGR_JAG(0); break;
-    case 1: MGR_JAG(1); break;
-    case 2: MGR_JAG(2); break;
-    case 3: MGR_JAG(3); break;
-    default: MGR_JAG(4); break;
+    // on the coarse-grid sweep); 4096 with the 16-bit columns' second 2 KB table
+    // (slot bases).  FP32 8192, and 4096 with the 16-bit columns (whose slot
+    // bases take 32 more registers at 8192: three waves per SIMD, sweep +60 %)
+#define MGR_JAG(IX, LDSN, M, CI)                                                                                  \
+    k_jag_stream<T, IX, M, LDSN><<<g, kJagRows, 0, s>>>(A.nrows, A.rp, CI, J.sb, jag_vals<T>(J), J.rows, J.bst, J.st, \
+                                                        x, r, d, y, y2)
+#define MGR_JAG_MODES(IX, LDSN, CI)                 \
+    switch (mode) {                                 \
+    case 0: MGR_JAG(IX, LDSN, 0, CI); break;        \
+    case 1: MGR_JAG(IX, LDSN, 1, CI); break;        \
+    case 2: MGR_JAG(IX, LDSN, 2, CI); break;        \
+    case 3: MGR_JAG(IX, LDSN, 3, CI); break;        \
+    default: MGR_JAG(IX, LDSN, 4, CI); break;       \
     }
+    if (J.co) {
+        MGR_JAG_MODES(uint16_t, 4096, J.co)
+    } else {
+        MGR_JAG_MODES(int32_t, (sizeof(T) == 4 ? 8192 : 4864), J.ci)
+    }
+#undef MGR_JAG_MODES
 #undef MGR_JAG
 }
 
@@ -803,8 +869,10 @@ void launch_jag_count(const DCsr &A, int32_t *cnt, hipStream_t s) {
     if (g) k_jag_count<<<g, kJagRows, 0, s>>>(A.nrows, A.rp, cnt);
 }
 
-void launch_jag_fill(const DCsr &A, Jag &J, hipStream_t s) {
-    if (J.nblk) k_jag_fill<<<(unsigned)J.nblk, kJagRows, 0, s>>>(A.nrows, A.rp, A.ci, A.v, J.bst, J.st, J.rows, J.ci, J.v);
+void launch_jag_fill(const DCsr &A, Jag &J, int *bad, hipStream_t s) {
+    if (J.nblk)
+        k_jag_fill<<<(unsigned)J.nblk, kJagRows, 0, s>>>(A.nrows, A.rp, A.ci, A.v, J.bst, J.st, J.rows, J.ci, J.co,
+                                                         J.sb, J.v, bad);
 }
 
 template <typename T>

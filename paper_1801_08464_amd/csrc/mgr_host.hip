@@ -470,11 +470,17 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     launch_gather_i32(lv.nC, lv.clist, lv.glob, glob_next, h->stream);
 }
 
-// Classical AMG hierarchy on Atop (kept as its level 0): strength -> PMIS ->
-// classical interpolation -> Galerkin P^T (A P), down to a dense LU.
 // The row-block jagged copy of a long-row level matrix for the solve-phase
-// SpMV (rows longer than kJagMaxSlots keep the CSR stream kernel).
-void build_jag(mgr_handle *h, AmgHier &H, DCsr &A) {
+// SpMV (rows longer than kJagMaxSlots keep the CSR stream kernel).  Level 0 of
+// a mixed-precision hierarchy (c16) stores 16-bit column offsets where the
+// option asks for them and every slot's columns lie within 65535 of its
+// smallest: its rows keep the grid's stencil order, so a slot's columns are
+// close together, and the FP32 kernel gains from the smaller stream (8 -> 6
+// bytes per entry).  On the coarsened levels the decode outweighed the bytes,
+// and in FP64 (12 -> 10 bytes) the gain was under 1 % of a V-cycle.  Else 32-bit
+// columns; the 16-bit arrays of a failed attempt stay unused in the arena until
+// the hierarchy is rebuilt.
+void build_jag(mgr_handle *h, AmgHier &H, DCsr &A, bool c16) {
     if (!csr_long_rows(A)) return;
     reset_err(h);
     launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
@@ -491,9 +497,24 @@ void build_jag(mgr_handle *h, AmgHier &H, DCsr &A) {
     }
     J->st = dalloc<int32_t>(h, J->nst);
     J->rows = dalloc<int32_t>(h, A.nrows);
-    J->ci = dalloc<int32_t>(h, A.nnz);
     J->v = dalloc<double>(h, A.nnz);
-    launch_jag_fill(A, *J, h->stream);
+    bool wide = !(c16 && h->o.jag_index16);
+    if (!wide) {
+        J->co = dalloc<uint16_t>(h, A.nnz);
+        J->sb = dalloc<int32_t>(h, J->nst);
+        reset_err(h);
+        launch_jag_fill(A, *J, h->derr + 4, h->stream);
+        read_err(h);
+        wide = h->herr[4] != 0;
+        if (wide) {
+            J->co = nullptr;
+            J->sb = nullptr;
+        }
+    }
+    if (wide) {
+        J->ci = dalloc<int32_t>(h, A.nnz);
+        launch_jag_fill(A, *J, nullptr, h->stream);
+    }
     A.jag = J.get();
     H.jags.push_back(std::move(J));
 }
@@ -590,13 +611,15 @@ void build_tails(mgr_handle *h) {
         if (lv.ff) build_tail(h, *lv.ff);
 }
 
+// Classical AMG hierarchy on Atop (kept as its level 0): strength -> PMIS ->
+// classical interpolation -> Galerkin P^T (A P), down to a dense LU.
 void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
     const mgr_options &o = h->o;
     H.pre = pre;
     H.post = post;
     DCsr A = Atop;
     for (int k = 0;; ++k) {
-        build_jag(h, H, A);
+        build_jag(h, H, A, k == 0 && o.precision == 1);
         H.lev.emplace_back();
         AmgLevel &lv = H.lev.back();
         lv.A = A;
@@ -810,11 +833,14 @@ inline void acct(mgr_handle *h, double bytes) {
 
 double csr_bytes(const DCsr &A, int mode, double S) {
     // row pointers, or for a jagged copy the rank-to-row map, the slot tables
-    // and two row pointers and two table offsets per block
-    const double index = A.jag && csr_long_rows(A)
-                             ? 4.0 * (double)A.nrows + 4.0 * (double)A.jag->nst + 16.0 * (double)A.jag->nblk
+    // (with the 16-bit columns also the slot bases) and two row pointers and two
+    // table offsets per block
+    const bool jag = A.jag && csr_long_rows(A);
+    const bool c16 = jag && A.jag->co;
+    const double index = jag ? 4.0 * (double)A.nrows + (c16 ? 8.0 : 4.0) * (double)A.jag->nst +
+                                   16.0 * (double)A.jag->nblk
                              : 4.0 * (double)(A.nrows + 1);
-    double b = (double)A.nnz * (S + 4.0) + index + S * (double)A.ncols + S * (double)A.nrows;
+    double b = (double)A.nnz * (S + (c16 ? 2.0 : 4.0)) + index + S * (double)A.ncols + S * (double)A.nrows;
     if (mode == 1 || mode == 2) b += S * (double)A.nrows;
     if (mode == 3) b += 2.0 * S * (double)A.nrows;
     return b;
@@ -1317,6 +1343,7 @@ int check_options(const mgr_options *o, std::string &why) {
     else if (o->frelax_amg_pre < 0 || o->frelax_amg_pre > 8 || o->frelax_amg_post < 0 || o->frelax_amg_post > 8)
         why = "frelax_amg_pre/post in [0, 8]";
     else if (o->cycle_post != 0 && o->cycle_post != 1) why = "cycle_post must be 0 or 1";
+    else if (o->jag_index16 != 0 && o->jag_index16 != 1) why = "jag_index16 must be 0 or 1";
     else return MGR_OK;
     return MGR_E_INVALID;
 }
@@ -1573,6 +1600,7 @@ void mgr_default_options(mgr_options *o) {
     o->frelax_amg_pre = 1;
     o->frelax_amg_post = 1;
     o->cycle_post = 0;
+    o->jag_index16 = 1;
 }
 
 int mgr_setup(const mgr_csr *A, int block_size, const int32_t *cf_labels, const mgr_options *opts,

@@ -25,7 +25,9 @@ constexpr int kJagRows = 256;
 constexpr int kJagMaxSlots = 508;  // longest row a jagged copy takes (the slot table fits 2 KB of LDS)
 struct Jag {
     int64_t nblk = 0, nst = 0;
-    int32_t *ci = nullptr;   // nnz, jagged order
+    int32_t *ci = nullptr;   // nnz, jagged order (null where co holds the columns)
+    uint16_t *co = nullptr;  // nnz, jagged order: column - sb[slot] (16-bit form)
+    int32_t *sb = nullptr;   // nst, parallel to st: each slot's smallest column (16-bit form)
     double *v = nullptr;     // nnz, jagged order
     float *vf = nullptr;
     int32_t *rows = nullptr; // n: row of each rank (global row index)
@@ -303,9 +305,11 @@ void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *
 // matrices that get a jagged copy).
 bool csr_long_rows(const DCsr &A);
 // Jagged copy: per-block longest row (maxlen + 1 into cnt[b]), then, with the
-// exclusive scan of cnt in bst, the ranks, slot tables and the reordered entries.
+// exclusive scan of cnt in bst, the ranks, slot tables and the reordered entries
+// (columns into J.co and J.sb where J.co is set, else into J.ci; *bad = 1 when a
+// 16-bit offset overflows).
 void launch_jag_count(const DCsr &A, int32_t *cnt, hipStream_t s);
-void launch_jag_fill(const DCsr &A, Jag &J, hipStream_t s);
+void launch_jag_fill(const DCsr &A, Jag &J, int *bad, hipStream_t s);
 template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s);
 // y = A x and y2 = y / d (restriction that also starts the next level's Jacobi sweeps)
