@@ -307,14 +307,15 @@ __global__ void k_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, co
 }
 
 __global__ void k_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
-                            const int32_t *Frp, int32_t *Fci, double *Fv) {
+                            const int32_t *Frp, int32_t *Fci, double *Fv, int fnum) {
     int64_t i = gtid();
     if (i >= n) return;
     int q = Frp[i];
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
         const int j = ci[p];
-        if (fmap[j] < 0) continue;
-        Fci[q] = j;
+        const int f = fmap[j];
+        if (f < 0) continue;
+        Fci[q] = fnum ? f : j;
         Fv[q] = v[p];
         q++;
     }
@@ -1076,8 +1077,8 @@ void launch_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, const in
     if (n > 0) k_fcol_count<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, fmap, cnt);
 }
 void launch_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
-                      const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s) {
-    if (n > 0) k_fcol_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, fmap, Frp, Fci, Fv);
+                      const int32_t *Frp, int32_t *Fci, double *Fv, bool fnum, hipStream_t s) {
+    if (n > 0) k_fcol_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, fmap, Frp, Fci, Fv, fnum ? 1 : 0);
 }
 int spgemm_max_row() { return kWave * kSpgChunks; }
 void launch_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx, hipStream_t s) {

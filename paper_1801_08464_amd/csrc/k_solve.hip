@@ -43,6 +43,9 @@ __device__ inline int64_t xcd_grouped_block() {
 
 // The per-row operands of the output step (the lanes kernel loads them before
 // the row's sum so that their latency overlaps it).
+// Mode 5 (y = e_F + A x, the prolongation that also writes the F-relaxation's
+// correction, kept compact by F index, with zeros on the C points): r holds the
+// compact correction and d carries the int32 F index map (-1 on C points).
 template <typename T, int MODE>
 struct RowIn {
     T a = 0, b = 0, c = 0;
@@ -50,6 +53,10 @@ struct RowIn {
                                 const T *__restrict__ d, const T *__restrict__ y) {
         if (MODE == 1) a = r[row];
         if (MODE == 2) a = y[row];
+        if (MODE == 5) {
+            const int f = reinterpret_cast<const int32_t *>(d)[row];
+            a = f >= 0 ? r[f] : (T)0;
+        }
         if (MODE == 3) {
             a = x[row];
             b = r[row];
@@ -59,7 +66,7 @@ struct RowIn {
     __device__ inline void store(int64_t row, T acc, T *__restrict__ y, T *__restrict__ y2) const {
         if (MODE == 0) y[row] = acc;
         else if (MODE == 1) y[row] = a - acc;
-        else if (MODE == 2) y[row] = a + acc;
+        else if (MODE == 2 || MODE == 5) y[row] = a + acc;
         else if (MODE == 3) y[row] = a + (b - acc) / c;
         else {
             y[row] = acc;
@@ -452,6 +459,28 @@ __global__ void k_frelax_first(int64_t n, const int32_t *__restrict__ fmap, cons
     e[i] = f >= 0 ? dinv[f] * r[i] : (T)0;
 }
 
+// The Jacobi F-relaxation from e = 0 kept compact: eF[f] = dinv[f] r[flist[f]]
+template <typename T>
+__global__ void k_frelax_first_compact(int64_t nF, const int32_t *__restrict__ flist, const T *__restrict__ dinv,
+                                       const T *__restrict__ r, T *__restrict__ eF) {
+    const int64_t f = gtid();
+    if (f >= nF) return;
+    eF[f] = dinv[f] * r[flist[f]];
+}
+
+// The prolongation with P the injection of the C points (W_p = 0) and the
+// F-relaxation's correction kept compact: e[i] = eF[fmap[i]] on F points,
+// 0 + e_c[cmap[i]] on C points
+template <typename T>
+__global__ void k_prolong_inject_compact(int64_t n, const int32_t *__restrict__ fmap,
+                                         const int32_t *__restrict__ cmap, const T *__restrict__ eF,
+                                         const T *__restrict__ ec, T *__restrict__ e) {
+    const int64_t i = gtid();
+    if (i >= n) return;
+    const int f = fmap[i];
+    e[i] = f >= 0 ? eF[f] : (T)0 + ec[cmap[i]];
+}
+
 template <typename T>
 __global__ void k_frelax_scatter(int64_t nF, const int32_t *__restrict__ flist, const T *__restrict__ dinv,
                                  const T *__restrict__ t, T *__restrict__ e) {
@@ -754,7 +783,8 @@ static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T
     case 1: MGR_STREAM(1); break;
     case 2: MGR_STREAM(2); break;
     case 3: MGR_STREAM(3); break;
-    default: MGR_STREAM(4); break;
+    case 4: MGR_STREAM(4); break;
+    default: MGR_STREAM(5); break;
     }
 #undef MGR_STREAM
 }
@@ -784,7 +814,8 @@ static void jag_rows(int mode, const DCsr &A, const T *x, const T *r, const T *d
     case 1: MGR_JAG(IX, LDSN, 1, CI); break;        \
     case 2: MGR_JAG(IX, LDSN, 2, CI); break;        \
     case 3: MGR_JAG(IX, LDSN, 3, CI); break;        \
-    default: MGR_JAG(IX, LDSN, 4, CI); break;       \
+    case 4: MGR_JAG(IX, LDSN, 4, CI); break;        \
+    default: MGR_JAG(IX, LDSN, 5, CI); break;       \
     }
     if (J.co) {
         MGR_JAG_MODES(uint16_t, 4096, J.co)
@@ -856,7 +887,8 @@ static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T 
     case 1: csr_lanes<T, 1>(A, lanes, vals, x, r, d, y, y2, s); break;
     case 2: csr_lanes<T, 2>(A, lanes, vals, x, r, d, y, y2, s); break;
     case 3: csr_lanes<T, 3>(A, lanes, vals, x, r, d, y, y2, s); break;
-    default: csr_lanes<T, 4>(A, lanes, vals, x, r, d, y, y2, s); break;
+    case 4: csr_lanes<T, 4>(A, lanes, vals, x, r, d, y, y2, s); break;
+    default: csr_lanes<T, 5>(A, lanes, vals, x, r, d, y, y2, s); break;
     }
 }
 
@@ -941,6 +973,17 @@ void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T 
 }
 
 template <typename T>
+void launch_frelax_first_compact(int64_t nF, const int32_t *flist, const T *dinv, const T *r, T *eF, hipStream_t s) {
+    if (nF > 0) k_frelax_first_compact<T><<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, dinv, r, eF);
+}
+
+template <typename T>
+void launch_prolong_inject_compact(int64_t n, const int32_t *fmap, const int32_t *cmap, const T *eF, const T *ec,
+                                   T *e, hipStream_t s) {
+    if (n > 0) k_prolong_inject_compact<T><<<nblocks(n, BT), BT, 0, s>>>(n, fmap, cmap, eF, ec, e);
+}
+
+template <typename T>
 void launch_frelax_scatter(int64_t nF, const int32_t *flist, const T *dinv, const T *t, T *e, hipStream_t s) {
     if (nF > 0) k_frelax_scatter<T><<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, dinv, t, e);
 }
@@ -987,6 +1030,10 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
                                            const T *, T *, hipStream_t);                                        \
     template void launch_block_apply<T>(int64_t, int, const T *, const T *, T *, bool, hipStream_t);            \
     template void launch_frelax_first<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);     \
+    template void launch_frelax_first_compact<T>(int64_t, const int32_t *, const T *, const T *, T *,           \
+                                                 hipStream_t);                                                  \
+    template void launch_prolong_inject_compact<T>(int64_t, const int32_t *, const int32_t *, const T *,        \
+                                                   const T *, T *, hipStream_t);                                \
     template void launch_frelax_scatter<T>(int64_t, const int32_t *, const T *, const T *, T *, hipStream_t);   \
     template void launch_div<T>(int64_t, const T *, const T *, T *, hipStream_t);                               \
     template void launch_gather<T>(int64_t, const int32_t *, const T *, T *, hipStream_t);                      \

@@ -406,16 +406,19 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     }
     // the F columns of A (all rows) for the residual that precedes the
     // restriction, at the levels where e is zero on the C points there (no global
-    // relaxation, pre-smoothing cycle)
+    // relaxation, pre-smoothing cycle); with one F-sweep the correction stays
+    // compact and the columns are its F indices
     if (lv.nF > 0 && !h->o.cycle_post && !(l == 0 && h->o.global_relax)) {
+        lv.fcompact = h->o.f_sweeps == 1;
         Tmp<int32_t> cnt(h, n);
         launch_fcol_count(n, A.rp, A.ci, lv.fmap, cnt.p, h->stream);
-        lv.AcF.nrows = lv.AcF.ncols = n;
+        lv.AcF.nrows = n;
+        lv.AcF.ncols = lv.fcompact ? lv.nF : n;
         lv.AcF.rp = dalloc<int32_t>(h, n + 1);
         lv.AcF.nnz = scan(h, cnt.p, lv.AcF.rp, n);
         lv.AcF.ci = dalloc<int32_t>(h, lv.AcF.nnz);
         lv.AcF.v = dalloc<double>(h, lv.AcF.nnz);
-        launch_fcol_fill(n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, h->stream);
+        launch_fcol_fill(n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, lv.fcompact, h->stream);
     }
     // optional F-relaxation by one AMG V-cycle on A_FF
     if (((h->o.frelax_amg_mask >> l) & 1) && lv.nF > 0) {
@@ -712,14 +715,17 @@ void alloc_work(mgr_handle *h, bool update = false) {
     const bool mixed = h->o.precision == 1;
     for (size_t l = 0; l < h->lev.size() && !update; ++l) {
         MgrLevel &lv = h->lev[l];
+        const bool eF = lv.fcompact && !lv.ff;  // the Jacobi relaxation's compact correction
         if (mixed) {
             lv.rf = dalloc<float>(h, lv.n);
             lv.ef = dalloc<float>(h, lv.n);
             lv.tf = dalloc<float>(h, lv.n);
+            if (eF) lv.eFf = dalloc<float>(h, lv.nF);
         } else {
             lv.r = dalloc<double>(h, lv.n);
             lv.e = dalloc<double>(h, lv.n);
             lv.t = dalloc<double>(h, lv.n);
+            if (eF) lv.eF = dalloc<double>(h, lv.nF);
         }
     }
     auto amg_work = [&](AmgHier &H) {
@@ -789,6 +795,7 @@ struct P_<double> {
     static double *r(MgrLevel &l) { return l.r; }
     static double *e(MgrLevel &l) { return l.e; }
     static double *t(MgrLevel &l) { return l.t; }
+    static double *eF(MgrLevel &l) { return l.eF; }
     static double *r(AmgLevel &l) { return l.r; }
     static double *x(AmgLevel &l) { return l.x; }
     static double *x2(AmgLevel &l) { return l.x2; }
@@ -805,6 +812,7 @@ struct P_<float> {
     static float *r(MgrLevel &l) { return l.rf; }
     static float *e(MgrLevel &l) { return l.ef; }
     static float *t(MgrLevel &l) { return l.tf; }
+    static float *eF(MgrLevel &l) { return l.eFf; }
     static float *r(AmgLevel &l) { return l.rf; }
     static float *x(AmgLevel &l) { return l.xf; }
     static float *x2(AmgLevel &l) { return l.x2f; }
@@ -1082,6 +1090,45 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
     };
     const bool global = l == 0 && h->o.global_relax;
     const double gbytes = (double)h->bs * h->bs * S * h->ncell + 2.0 * S * n;
+    if (lv.fcompact) {
+        // one F-sweep from e = 0 with the correction kept by F index (the same
+        // products and sums as with it scattered into e, whose C entries are 0):
+        // F-relaxation, residual r - A_{:,F} e_F, coarse-grid correction, then
+        // e = e_F + P e_c in one pass
+        const T *eF;
+        if (lv.ff) {
+            AmgLevel &f0 = lv.ff->lev[0];
+            T *rF = P_<T>::r(f0), *dF = P_<T>::x(f0);
+            if (amg_takes_x0<T>(*lv.ff)) {
+                launch_gather_div<T>(lv.nF, lv.flist, r, P_<T>::l1(f0), rF, amg_x0_buffer<T>(*lv.ff, 0, dF), s);
+                acct(h, 4.0 * nF + 4.0 * S * nF);
+                amg_cycle<T>(h, *lv.ff, 0, rF, dF, true);
+            } else {
+                launch_gather<T>(lv.nF, lv.flist, r, rF, s);
+                acct(h, 4.0 * nF + 2.0 * S * nF);
+                amg_cycle<T>(h, *lv.ff, 0, rF, dF);
+            }
+            eF = dF;
+        } else {
+            T *e1 = P_<T>::eF(lv);
+            launch_frelax_first_compact<T>(lv.nF, lv.flist, dinv, r, e1, s);
+            acct(h, 4.0 * nF + 4.0 * S * nF);
+            eF = e1;
+        }
+        // AcF's columns are F indices: the gathered vector is e_F (nF long)
+        launch_csr<T>(1, lv.AcF, P_<T>::v(lv.AcF), eF, r, nullptr, t, s);
+        acct(h, csr_bytes(lv.AcF, 1, S));
+        coarse_correction(t);
+        if (lv.P.nnz == lv.nC) {
+            launch_prolong_inject_compact<T>(lv.n, lv.fmap, lv.cmap, eF, ec, e, s);
+            acct(h, 8.0 * n + S * nF + S * (double)lv.nC + S * n);
+        } else {
+            launch_csr<T>(5, lv.P, P_<T>::v(lv.P), ec, eF, reinterpret_cast<const T *>(lv.fmap), e, s);
+            // the gathered e_c and the written e (mode 0's count), the F map and e_F
+            acct(h, csr_bytes(lv.P, 0, S) + 4.0 * n + S * nF);
+        }
+        return;
+    }
     if (h->o.cycle_post) {
         // eq. MGR-post: coarse-grid correction from e = 0, then the smoother M_f of
         // the pre-smoothing form with its steps in the same order (global
@@ -1361,7 +1408,7 @@ void update_mgr_level(mgr_handle *h, int l, DCsr &Anext) {
     fdiag_inverse(h, l);
     if (lv.AF.v) launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
     if (lv.AcF.v)
-        launch_fcol_fill(lv.n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, h->stream);
+        launch_fcol_fill(lv.n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, lv.fcompact, h->stream);
     if (lv.Aff.v) {  // the level relaxes its F points with an AMG cycle on A_FF
         launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, lv.Aff.rp, lv.Aff.ci, lv.Aff.v, h->stream);
         lv.ff = std::make_shared<AmgHier>();

@@ -131,7 +131,15 @@ struct MgrLevel {
     int32_t *cmap = nullptr;  // level row -> coarse index (-1 on F points)
     bool aff_diag = false;  // A_FF diagonal: the F-relaxation may update in place
     DCsr AF;                // compact copy of the F rows (all columns), row f = level row flist[f]
-    DCsr AcF;               // the F columns of A (all rows, level numbering): r - A e when e_C = 0
+    DCsr AcF;               // the F columns of A (all rows): r - A e when e_C = 0; columns numbered by
+                            // F index where fcompact, else level rows
+    // one F-sweep from e = 0 in the pre-smoothing cycle without the global
+    // relaxation: the correction stays compact by F index (eF, or the F-block
+    // AMG's output), the residual gathers it through AcF, and the prolongation
+    // writes e = correction + P e_c in one pass
+    bool fcompact = false;
+    double *eF = nullptr;   // nF: the Jacobi F-relaxation's compact correction
+    float *eFf = nullptr;
     int flanes = 1;         // threads per F row in the F-point residual / relaxation kernels
     DCsr Aff;                     // A_FF (level 0 of ff), kept with the pattern-bound data
     std::shared_ptr<AmgHier> ff;  // AMG V-cycle on A_FF as the F-relaxation (else Jacobi)
@@ -263,8 +271,9 @@ void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const i
                     const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s);
 void launch_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt,
                        hipStream_t s);
+// the F columns of every row; fnum: columns as F indices (fmap[j]) instead of level rows
 void launch_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
-                      const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s);
+                      const int32_t *Frp, int32_t *Fci, double *Fv, bool fnum, hipStream_t s);
 // SpGEMM C = A B, canonical ascending-k summation.  pass 0 counts into cnt, pass 1 fills.
 // group = lanes per output row (8, 16, 32, 64); rows of A may hold up to group * 8 entries.
 int spgemm_max_row();
@@ -325,6 +334,14 @@ template <typename T>
 void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, bool add, hipStream_t s);
 template <typename T>
 void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T *r, T *e, hipStream_t s);
+// eF[f] = dinv[f] r[flist[f]]: the same relaxation, the correction kept by F index
+template <typename T>
+void launch_frelax_first_compact(int64_t nF, const int32_t *flist, const T *dinv, const T *r, T *eF, hipStream_t s);
+// e[i] = eF[fmap[i]] (F points) or 0 + ec[cmap[i]] (C points): the injection
+// prolongation applied to a compact F-relaxation correction
+template <typename T>
+void launch_prolong_inject_compact(int64_t n, const int32_t *fmap, const int32_t *cmap, const T *eF, const T *ec,
+                                   T *e, hipStream_t s);
 template <typename T>
 void launch_frelax_scatter(int64_t nF, const int32_t *flist, const T *dinv, const T *t, T *e, hipStream_t s);
 // e[i] += dinv[f] (r[i] - (A e)[i]), i = flist[f], A the compact F-row copy; needs A_FF diagonal
