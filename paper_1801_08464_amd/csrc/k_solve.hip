@@ -459,6 +459,32 @@ __global__ void k_frelax_first(int64_t n, const int32_t *__restrict__ fmap, cons
     e[i] = f >= 0 ? dinv[f] * r[i] : (T)0;
 }
 
+// The mixed-precision cycle's FP64 boundary folded into its first and last
+// level-0 steps.  In: rf = (float) r64, then e = B^{-1} rf per 3x3 cell block
+// (the products and sums of k_block_apply3).  Out: the W_p = 0 prolongation
+// e_C += e_c and z = (double) e in one pass over the level's rows.
+__global__ void k_block_apply3_in64(int64_t ncell, const float *__restrict__ B, const double *__restrict__ r64,
+                                    float *__restrict__ rf, float *__restrict__ e) {
+    const int64_t c = gtid();
+    if (c >= ncell) return;
+    const float r0 = (float)r64[3 * c], r1 = (float)r64[3 * c + 1], r2 = (float)r64[3 * c + 2];
+    rf[3 * c] = r0;
+    rf[3 * c + 1] = r1;
+    rf[3 * c + 2] = r2;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        e[3 * c + q] = B[(3 * q) * ncell + c] * r0 + B[(3 * q + 1) * ncell + c] * r1 + B[(3 * q + 2) * ncell + c] * r2;
+}
+
+__global__ void k_scatter_add_out64(int64_t n, const int32_t *__restrict__ cmap, const float *__restrict__ ec,
+                                    const float *__restrict__ e, double *__restrict__ z) {
+    const int64_t i = gtid();
+    if (i >= n) return;
+    const int c = cmap[i];
+    const float v = c >= 0 ? e[i] + ec[c] : e[i];
+    z[i] = (double)v;
+}
+
 // The Jacobi F-relaxation from e = 0 kept compact: eF[f] = dinv[f] r[flist[f]]
 template <typename T>
 __global__ void k_frelax_first_compact(int64_t nF, const int32_t *__restrict__ flist, const T *__restrict__ dinv,
@@ -970,6 +996,16 @@ void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, 
 template <typename T>
 void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T *r, T *e, hipStream_t s) {
     if (n > 0) k_frelax_first<T><<<nblocks(n, BT), BT, 0, s>>>(n, fmap, dinv, r, e);
+}
+
+void launch_block_apply3_in64(int64_t ncell, const float *binv, const double *r64, float *rf, float *e,
+                              hipStream_t s) {
+    if (ncell > 0) k_block_apply3_in64<<<nblocks(ncell, BT), BT, 0, s>>>(ncell, binv, r64, rf, e);
+}
+
+void launch_scatter_add_out64(int64_t n, const int32_t *cmap, const float *ec, const float *e, double *z,
+                              hipStream_t s) {
+    if (n > 0) k_scatter_add_out64<<<nblocks(n, BT), BT, 0, s>>>(n, cmap, ec, e, z);
 }
 
 template <typename T>

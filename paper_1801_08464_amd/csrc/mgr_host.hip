@@ -12,6 +12,7 @@
 #include <new>
 
 #include "mgr_impl.h"
+#include <type_traits>
 
 using namespace mgr;
 
@@ -1007,8 +1008,16 @@ void amg_cycle(mgr_handle *h, AmgHier &H, int k, const T *r, T *x, bool x0_ready
 
 // x0_ready (l == L only): the restriction into the coarse grid already wrote the
 // first Jacobi iterate of the coarse-grid AMG cycle
+// The mixed-precision cycle's FP64 ends, taken by level 0 where its first and
+// last steps can absorb the casts: in is cast into rf (the level's r)
+struct Io64 {
+    const double *in = nullptr;
+    float *rf = nullptr;
+    double *out = nullptr;
+};
+
 template <typename T>
-void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
+void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, const Io64 *io = nullptr) {
     if (l == h->L) {
         amg_cycle<T>(h, h->cg, 0, r, e, x0_ready);
         return;
@@ -1146,9 +1155,19 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
     // (1) global relaxation with the cell blocks (level 0)
     bool have = false;
     if (global) {
-        launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), r, e, false, s);
-        acct(h, gbytes);
-        have = true;
+        if constexpr (std::is_same<T, float>::value) {
+            if (io) {
+                // the FP64 input cast in the same pass
+                launch_block_apply3_in64(h->ncell, P_<T>::binv(h), io->in, io->rf, e, s);
+                acct(h, gbytes + 8.0 * n);
+                have = true;
+            }
+        }
+        if (!have) {
+            launch_block_apply<T>(h->ncell, h->bs, P_<T>::binv(h), r, e, false, s);
+            acct(h, gbytes);
+            have = true;
+        }
     }
     // (2) F-relaxation
     have = frelax(have);
@@ -1162,6 +1181,14 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
     else if (l == 0) fine_op<T>(h, 1, e, r, t);
     else csr<T>(h, 1, lv.A, Av, e, r, nullptr, t);
     coarse_correction(t);
+    if constexpr (std::is_same<T, float>::value) {
+        if (io && lv.P.nnz == lv.nC) {
+            // e_C += e_c and the FP64 output cast in one pass
+            launch_scatter_add_out64(lv.n, lv.cmap, ec, e, io->out, s);
+            acct(h, 8.0 * n + 4.0 * (double)lv.nC + 8.0 * n);
+            return;
+        }
+    }
     if (lv.P.nnz == lv.nC) {
         // W_p = 0 (every F row of P empty, the C rows the identity): the
         // prolongation is e_C += e_c
@@ -1169,6 +1196,12 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false) {
         acct(h, 4.0 * (double)lv.nC + 3.0 * S * (double)lv.nC);
     } else {
         csr<T>(h, 2, lv.P, P_<T>::v(lv.P), ec, nullptr, nullptr, e);
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        if (io) {
+            launch_cast_f32_f64(e, io->out, lv.n, s);
+            acct(h, 12.0 * n);
+        }
     }
 }
 
@@ -1180,10 +1213,20 @@ void apply_prec(mgr_handle *h, const double *v, double *z) {
     if (h->o.precision == 1) {
         float *rf = h->L > 0 ? h->lev[0].rf : h->cg.lev[0].rf;
         float *ef = h->L > 0 ? h->lev[0].ef : h->cg.lev[0].xf;
-        launch_cast_f64_f32(v, rf, h->n, h->stream);
-        mgr_cycle<float>(h, 0, rf, ef);
-        launch_cast_f32_f64(ef, z, h->n, h->stream);
-        acct(h, 24.0 * h->n);
+        if (h->L > 0 && h->bs == 3 && h->o.global_relax && !h->o.cycle_post) {
+            // level 0 opens with the cell-block relaxation of r and ends with a
+            // prolongation: both casts ride on those passes
+            Io64 io;
+            io.in = v;
+            io.rf = rf;
+            io.out = z;
+            mgr_cycle<float>(h, 0, rf, ef, false, &io);
+        } else {
+            launch_cast_f64_f32(v, rf, h->n, h->stream);
+            mgr_cycle<float>(h, 0, rf, ef);
+            launch_cast_f32_f64(ef, z, h->n, h->stream);
+            acct(h, 24.0 * h->n);
+        }
     } else {
         mgr_cycle<double>(h, 0, v, z);
     }

@@ -334,6 +334,12 @@ template <typename T>
 void launch_block_apply(int64_t ncell, int bs, const T *binv, const T *r, T *e, bool add, hipStream_t s);
 template <typename T>
 void launch_frelax_first(int64_t n, const int32_t *fmap, const T *dinv, const T *r, T *e, hipStream_t s);
+// The mixed-precision cycle's FP64 input and output folded into level 0 (3x3
+// cells): rf = (float) r64 and e = B^{-1} rf; z = (double)(e + e_c on C points)
+void launch_block_apply3_in64(int64_t ncell, const float *binv, const double *r64, float *rf, float *e,
+                              hipStream_t s);
+void launch_scatter_add_out64(int64_t n, const int32_t *cmap, const float *ec, const float *e, double *z,
+                              hipStream_t s);
 // eF[f] = dinv[f] r[flist[f]]: the same relaxation, the correction kept by F index
 template <typename T>
 void launch_frelax_first_compact(int64_t nF, const int32_t *flist, const T *dinv, const T *r, T *eF, hipStream_t s);
