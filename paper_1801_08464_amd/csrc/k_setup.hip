@@ -22,31 +22,66 @@ __device__ inline double row_diag(const int32_t *rp, const int32_t *ci, const do
 }
 
 // ---------------- validation ----------------
+// Counters and flags over a whole pass are reduced per workgroup, then one
+// atomic per workgroup: same-address device atomics serialise across the XCDs
+// (one per wavefront cost ~250 us per 2 M rows), so these kernels stride over
+// their rows with at most kReduceBlocks workgroups.
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBT = 256;
+
+__device__ inline int block_sum_i32(int v, int *sh) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
+    __syncthreads();
+    int t = 0;
+    for (int k = 0; k < kReduceBT / kWave; ++k) t += sh[k];
+    return t;
+}
+
+__device__ inline unsigned block_or_u32(unsigned v, int *sh) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v |= (unsigned)__shfl_xor((int)v, o);
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = (int)v;
+    __syncthreads();
+    unsigned t = 0;
+    for (int k = 0; k < kReduceBT / kWave; ++k) t |= (unsigned)sh[k];
+    return t;
+}
+
 // err[0] |= 1 on a bad row; err[1] = max label; err[2] |= 1 on a label outside [0, 31]
-__global__ void k_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const int32_t *lab,
-                           int *err) {
-    int64_t i = gtid();
-    if (i >= n) i = n - 1;  // surplus lanes repeat the last row (idempotent), so whole wavefronts reduce
-    int a = rp[i], b = rp[i + 1];
-    bool bad = a < 0 || b < a || (int64_t)b > nnz;
-    if (!bad) {
-        // no early exit: the column loads of a row do not wait for each other
-        int prev = -1;
-        for (int p = a; p < b; ++p) {
-            const int c = ci[p];
-            bad = bad || c <= prev || (int64_t)c >= n;  // c <= prev also catches c < 0
-            prev = c;
+__global__ void __launch_bounds__(kReduceBT) k_validate(int64_t n, int64_t nnz, const int32_t *rp,
+                                                        const int32_t *ci, const int32_t *lab, int *err) {
+    __shared__ int sh[kReduceBT / kWave];
+    bool bad = false, badlab = false;
+    unsigned bits = 0;  // the labels present
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * kReduceBT) {
+        const int a = rp[i], b = rp[i + 1];
+        bool rbad = a < 0 || b < a || (int64_t)b > nnz;
+        if (!rbad) {
+            // no early exit: the column loads of a row do not wait for each other
+            int prev = -1;
+            for (int p = a; p < b; ++p) {
+                const int c = ci[p];
+                rbad = rbad || c <= prev || (int64_t)c >= n;  // c <= prev also catches c < 0
+                prev = c;
+            }
+        }
+        bad = bad || rbad;
+        if (lab) {
+            const int L = lab[i];
+            if (L < 0 || L > 31) badlab = true;
+            else bits |= 1u << L;
         }
     }
-    if (bad) atomicOr(&err[0], 1);
-    if (lab) {
-        const int L = lab[i];
-        if (L < 0 || L > 31) atomicOr(&err[2], 1);
-        // the labels present, as a bit set reduced over the wavefront: one atomic per wavefront
-        unsigned bits = (L >= 0 && L <= 31) ? (1u << L) : 0u;
-#pragma unroll
-        for (int o = kWave / 2; o > 0; o >>= 1) bits |= (unsigned)__shfl_xor((int)bits, o);
-        if ((threadIdx.x & (kWave - 1)) == 0 && bits) atomicMax(&err[1], 31 - __builtin_clz(bits));
+    const unsigned f = block_or_u32((bad ? 1u : 0u) | (badlab ? 2u : 0u), sh);
+    const unsigned lb = block_or_u32(bits, sh);
+    if (threadIdx.x == 0) {
+        if (f & 1u) atomicOr(&err[0], 1);
+        if (f & 2u) atomicOr(&err[2], 1);
+        if (lb) atomicMax(&err[1], 31 - __builtin_clz(lb));
     }
 }
 
@@ -627,16 +662,16 @@ __global__ void k_pmis_select(int64_t n, const int32_t *Srp, const int32_t *Sci,
 }
 
 // new C points become C; undecided points that strongly depend on a new C point become F.
-// counters[0] += undecided left, counters[1] += new C points (counted per wavefront,
+// counters[0] += undecided left, counters[1] += new C points (reduced per workgroup,
 // one atomic each).
-__global__ void k_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *newc,
-                              int32_t *state, int *counters) {
-    const int64_t i = gtid();
-    bool und = false, nc = false;
-    if (i < n) {
+__global__ void __launch_bounds__(kReduceBT) k_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci,
+                                                           const int32_t *newc, int32_t *state, int *counters) {
+    __shared__ int sh[kReduceBT / kWave];
+    int und = 0, nc = 0;
+    for (int64_t i = gtid(); i < n; i += (int64_t)gridDim.x * kReduceBT) {
         if (newc[i]) {
             state[i] = 1;
-            nc = true;
+            ++nc;
         } else if (state[i] == 0) {
             bool f = false;
             for (int p = Srp[i]; p < Srp[i + 1]; ++p)
@@ -645,11 +680,11 @@ __global__ void k_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci,
                     break;
                 }
             if (f) state[i] = -1;
-            else und = true;
+            else ++und;
         }
     }
-    const int cu = __popcll(__ballot(und)), cc = __popcll(__ballot(nc));
-    if ((threadIdx.x & (kWave - 1)) == 0) {
+    const int cu = block_sum_i32(und, sh), cc = block_sum_i32(nc, sh);
+    if (threadIdx.x == 0) {
         if (cu) atomicAdd(&counters[0], cu);
         if (cc) atomicAdd(&counters[1], cc);
     }
@@ -1012,7 +1047,8 @@ constexpr int BT = 256;
 
 void launch_validate(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const int32_t *lab, int *err,
                      hipStream_t s) {
-    if (n > 0) k_validate<<<nblocks(n, BT), BT, 0, s>>>(n, nnz, rp, ci, lab, err);
+    const int64_t g = nblocks(n, kReduceBT);
+    if (n > 0) k_validate<<<(unsigned)(g < kReduceBlocks ? g : kReduceBlocks), kReduceBT, 0, s>>>(n, nnz, rp, ci, lab, err);
 }
 void launch_csell_count(int64_t ncell, int bs, const int32_t *rp, int32_t *rowlen, hipStream_t s) {
     int64_t n = ncell * bs;
@@ -1145,7 +1181,10 @@ void launch_pmis_select(int64_t n, const int32_t *Srp, const int32_t *Sci, const
 }
 void launch_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci, const int32_t *newc, int32_t *state,
                         int *counters, hipStream_t s) {
-    if (n > 0) k_pmis_update<<<nblocks(n, BT), BT, 0, s>>>(n, Srp, Sci, newc, state, counters);
+    const int64_t g = nblocks(n, kReduceBT);
+    if (n > 0)
+        k_pmis_update<<<(unsigned)(g < kReduceBlocks ? g : kReduceBlocks), kReduceBT, 0, s>>>(n, Srp, Sci, newc, state,
+                                                                                             counters);
 }
 void launch_cf_flags(int64_t n, const int32_t *state, int32_t *isC, hipStream_t s) {
     if (n > 0) k_cf_flags<<<nblocks(n, BT), BT, 0, s>>>(n, state, isC);

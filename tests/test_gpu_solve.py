@@ -231,6 +231,28 @@ def test_status_codes_through_the_abi():
     g.close()
 
 
+def test_validation_covers_every_row_of_a_large_input():
+    # more rows than the validation kernel has threads (1024 workgroups of 256):
+    # a bad entry or label in the last rows is still caught
+    from paper_1801_08464_amd import binding as B
+    s = small_system((48, 48, 48), seed=2, region="ball")
+    assert s.n > 1024 * 256
+    print(f"[validation] n={s.n}", flush=True)
+    unsorted = s.indices.copy()
+    last = np.nonzero(np.diff(s.indptr) >= 2)[0][-1]  # the last row with two entries
+    assert last > 1024 * 256
+    a = s.indptr[last]
+    unsorted[[a, a + 1]] = unsorted[[a + 1, a]]
+    with pytest.raises(B.MGRError) as e:
+        gpu_solver(s.__class__(**{**s.__dict__, "indices": unsorted}))
+    assert e.value.code == B.E_INVALID
+    bad = s.labels.copy()
+    bad[-1] = 32
+    with pytest.raises(B.MGRError) as e:
+        gpu_solver(s.__class__(**{**s.__dict__, "labels": bad}))
+    assert e.value.code == B.E_INVALID
+
+
 def test_empty_system_is_rejected():
     # n = 0: the setup refuses it (no partial handle is returned)
     from paper_1801_08464_amd import binding as B
