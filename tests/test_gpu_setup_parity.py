@@ -9,10 +9,31 @@ from synth import make_config, make_poisson
 
 pytestmark = pytest.mark.gpu
 
+def long_row_system():
+    """A 12^3 system whose first pressure row also couples to the pressure of 300
+    other cells (row sum kept): the Galerkin products then hold rows of more
+    than 256 entries (up to 506 on AMG level 1), and the SpGEMM count recounts
+    with the group of the longest left-operand row."""
+    import scipy.sparse as sp
+    s = small_system((12, 12, 12), seed=5, sigma=2.0, frac=0.3, region="ball")
+    assert s.labels[0] == 3
+    A = sp.csr_matrix((s.data, s.indices, s.indptr), shape=(s.n, s.n))
+    cells = np.arange(5, 5 + 5 * 300, 5)
+    eps = 1e-3 * A[0, 0]
+    extra = sp.csr_matrix((np.r_[np.full(300, -eps), [300 * eps]], (np.zeros(301, int), np.r_[3 * cells, [0]])),
+                          shape=A.shape)
+    A = (A + extra).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return s.__class__(**{**s.__dict__, "indptr": A.indptr.astype(np.int32), "indices": A.indices.astype(np.int32),
+                          "data": A.data.astype(np.float64)})
+
+
 CASES = {
     "cfg1_32x32": lambda: make_config(1),
     "2d_37x29_band": lambda: small_system((37, 29), seed=8, sigma=2.0, frac=0.3, region="band"),
     "3d_13x11x9_ball": lambda: small_system((13, 11, 9), seed=4, sigma=2.0, frac=0.3, region="ball"),
+    "3d_12cube_long_row": long_row_system,
 }
 
 
