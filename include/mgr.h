@@ -85,11 +85,11 @@ typedef struct {
                                  with presmoothing", default); 1: post-smoothing form eq. MGR-post: the
                                  coarse-grid correction from e = 0 first, then the same smoother M_f as
                                  the pre-smoothing form: (level 0) the global relaxation, then F-relaxation */
-    int jag_index16;          /* storage of the solve-phase copy of each mixed-precision AMG hierarchy's
-                                 level-0 matrix when its rows are long (no effect on results, which are
-                                 bitwise the same either way): 1 (default) 16-bit column offsets from a
-                                 32-bit base per 256-row block and entry slot, where every offset fits (else
-                                 32-bit columns); 0 32-bit columns.  FP64 hierarchies keep 32-bit columns */
+    int index16;              /* column storage of the solve-phase copies (no effect on results, which are
+                                 bitwise the same either way): 1 (default) 16-bit column offsets from a 32-bit
+                                 base per slot where every offset of the matrix fits (else 32-bit columns),
+                                 in the level-0 operator's sliced ELL and in the long-row level-0 matrix of
+                                 each mixed-precision AMG hierarchy; 0 32-bit columns everywhere */
 } mgr_options;
 
 typedef struct {

@@ -35,7 +35,7 @@ class MgrOptions(C.Structure):
                 ("amg_coarse_max", C.c_int), ("dense_max", C.c_int), ("pmis_seed", C.c_uint64),
                 ("transpose", C.c_int), ("use_x0", C.c_int), ("frelax_amg_mask", C.c_int),
                 ("frelax_amg_pre", C.c_int), ("frelax_amg_post", C.c_int), ("cycle_post", C.c_int),
-                ("jag_index16", C.c_int)]
+                ("index16", C.c_int)]
 
 
 class MgrStats(C.Structure):

@@ -125,6 +125,26 @@ __global__ void k_csell_fill(int64_t ncell, int bs, const int32_t *rp, const int
     }
 }
 
+// one wavefront per slot of 64 lanes: the slot's smallest column (padding
+// excluded), then each lane's offset from it
+__global__ void k_csell_pack16(int64_t nslot, const int32_t *__restrict__ col, int32_t *__restrict__ sb,
+                               uint16_t *__restrict__ co, int *bad) {
+    const int64_t slot = gtid() / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (slot >= nslot) return;  // uniform per wavefront
+    const int c = col[slot * kWave + lane];
+    int m = c >= 0 ? c : INT_MAX;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const int y = __shfl_xor(m, o);
+        m = y < m ? y : m;
+    }
+    if (lane == 0) sb[slot] = m == INT_MAX ? 0 : m;
+    const unsigned off = c >= 0 ? (unsigned)(c - m) : 0xffffu;
+    if (c >= 0 && off >= 0xffffu) *bad = 1;
+    co[slot * kWave + lane] = (uint16_t)off;
+}
+
 // ---------------- global relaxation: cell-block inverses ----------------
 // planes: binv[(r*3+q)*ncell + c] = (B_c^{-1})_{rq}; det by cofactor expansion
 // along row 0 and inv_ij = cof_ji * (1/det).  err[3] = smallest singular cell.
@@ -1061,6 +1081,9 @@ void launch_csell_width(int64_t nslice, int bs, int64_t ncell, const int32_t *ro
 void launch_csell_fill(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v,
                        const int32_t *off, const int32_t *width, int32_t *col, double *val, hipStream_t s) {
     if (ncell > 0) k_csell_fill<<<nblocks(ncell * bs, BT), BT, 0, s>>>(ncell, bs, rp, ci, v, off, width, col, val);
+}
+void launch_csell_pack16(int64_t nslot, const int32_t *col, int32_t *sb, uint16_t *co, int *bad, hipStream_t s) {
+    if (nslot > 0) k_csell_pack16<<<nblocks(nslot * kWave, BT), BT, 0, s>>>(nslot, col, sb, co, bad);
 }
 void launch_block_inverse(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v, double *binv,
                           int *err, hipStream_t s) {

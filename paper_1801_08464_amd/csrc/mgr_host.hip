@@ -351,6 +351,20 @@ void build_csell(mgr_handle *h) {
     launch_fill_i32(S.col, -1, S.nslot * kWave, h->stream);
     launch_fill_f64(S.v, 0.0, S.nslot * kWave, h->stream);
     launch_csell_fill(S.ncell, S.bs, A.rp, A.ci, A.v, S.off, S.width, S.col, S.v, h->stream);
+    if (h->o.index16) {
+        // the 16-bit columns (a slot's lanes are 64 consecutive cells at one
+        // stencil position: their columns lie close together); the arrays of a
+        // failed attempt stay unused until the handle is destroyed
+        S.sb = dalloc<int32_t>(h, S.nslot);
+        S.co = dalloc<uint16_t>(h, S.nslot * kWave);
+        reset_err(h);
+        launch_csell_pack16(S.nslot, S.col, S.sb, S.co, h->derr + 4, h->stream);
+        read_err(h);
+        if (h->herr[4]) {
+            S.sb = nullptr;
+            S.co = nullptr;
+        }
+    }
 }
 
 void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post);
@@ -502,7 +516,7 @@ void build_jag(mgr_handle *h, AmgHier &H, DCsr &A, bool c16) {
     J->st = dalloc<int32_t>(h, J->nst);
     J->rows = dalloc<int32_t>(h, A.nrows);
     J->v = dalloc<double>(h, A.nnz);
-    bool wide = !(c16 && h->o.jag_index16);
+    bool wide = !(c16 && h->o.index16);
     if (!wide) {
         J->co = dalloc<uint16_t>(h, A.nnz);
         J->sb = dalloc<int32_t>(h, J->nst);
@@ -865,7 +879,10 @@ void fine_op(mgr_handle *h, int mode, const T *x, const T *r, T *y) {
         // values + columns of the true nonzeros, row pointers, x and y, plus r
         // for the residual form
         const double n = (double)h->n;
-        const double b = (double)h->A0s.nnz_true * (sizeof(T) + 4.0) + 4.0 * (n + 1) + 2.0 * n * sizeof(T) +
+        // (16-bit columns: 2 bytes per entry and the slot bases)
+        const double cb = h->A0s.co ? 2.0 * (double)h->A0s.nnz_true + 4.0 * (double)h->A0s.nslot
+                                    : 4.0 * (double)h->A0s.nnz_true;
+        const double b = (double)h->A0s.nnz_true * sizeof(T) + cb + 4.0 * (n + 1) + 2.0 * n * sizeof(T) +
                          (mode == 1 ? n * sizeof(T) : 0.0);
         h->tm[0].bytes += b;
         h->tm[0].launches++;
@@ -1433,7 +1450,7 @@ int check_options(const mgr_options *o, std::string &why) {
     else if (o->frelax_amg_pre < 0 || o->frelax_amg_pre > 8 || o->frelax_amg_post < 0 || o->frelax_amg_post > 8)
         why = "frelax_amg_pre/post in [0, 8]";
     else if (o->cycle_post != 0 && o->cycle_post != 1) why = "cycle_post must be 0 or 1";
-    else if (o->jag_index16 != 0 && o->jag_index16 != 1) why = "jag_index16 must be 0 or 1";
+    else if (o->index16 != 0 && o->index16 != 1) why = "index16 must be 0 or 1";
     else return MGR_OK;
     return MGR_E_INVALID;
 }
@@ -1690,7 +1707,7 @@ void mgr_default_options(mgr_options *o) {
     o->frelax_amg_pre = 1;
     o->frelax_amg_post = 1;
     o->cycle_post = 0;
-    o->jag_index16 = 1;
+    o->index16 = 1;
 }
 
 int mgr_setup(const mgr_csr *A, int block_size, const int32_t *cf_labels, const mgr_options *opts,

@@ -59,6 +59,11 @@ struct CSell {
     int32_t *col = nullptr;    // nslot*64 (-1 = padding)
     double *v = nullptr;
     float *vf = nullptr;
+    // 16-bit form of the columns (null where a slot's columns span more than
+    // 65534): sb[slot] = the slot's smallest column, co = column - sb (0xffff =
+    // padding)
+    int32_t *sb = nullptr;     // nslot
+    uint16_t *co = nullptr;    // nslot*64
 };
 
 struct AmgLevel {
@@ -245,6 +250,9 @@ void launch_csell_width(int64_t nslice, int bs, int64_t ncell, const int32_t *ro
                         hipStream_t s);
 void launch_csell_fill(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v,
                        const int32_t *off, const int32_t *width, int32_t *col, double *val, hipStream_t s);
+// the 16-bit form of the columns: per slot the smallest column and the offsets;
+// *bad = 1 where a slot's columns span more than 65534
+void launch_csell_pack16(int64_t nslot, const int32_t *col, int32_t *sb, uint16_t *co, int *bad, hipStream_t s);
 void launch_block_inverse(int64_t ncell, int bs, const int32_t *rp, const int32_t *ci, const double *v, double *binv,
                           int *err, hipStream_t s);
 void launch_level_flags(int64_t n, const int32_t *lab, int l, int32_t *isF, int32_t *isC, hipStream_t s);

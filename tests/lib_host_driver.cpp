@@ -76,7 +76,7 @@ int main() {
         {"frelax_amg_mask -1", [](mgr_options &p) { p.frelax_amg_mask = -1; }},
         {"frelax_amg_pre 9", [](mgr_options &p) { p.frelax_amg_pre = 9; }},
         {"cycle_post 2", [](mgr_options &p) { p.cycle_post = 2; }},
-        {"jag_index16 2", [](mgr_options &p) { p.jag_index16 = 2; }},
+        {"index16 2", [](mgr_options &p) { p.index16 = 2; }},
     };
     for (const Opt &c : opts) {
         mgr_options p = o;

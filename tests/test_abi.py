@@ -34,7 +34,7 @@ def test_host_only_entry_points():
     assert (o.restart, o.max_iter, o.rp_type, o.global_relax, o.f_sweeps) == (30, 400, 0, 1, 1)
     assert (o.amg_theta, o.amg_pre, o.amg_post, o.amg_coarse_max) == (0.25, 2, 2, 64)
     assert (o.frelax_amg_mask, o.frelax_amg_pre, o.frelax_amg_post, o.cycle_post) == (0, 1, 1, 0)
-    assert o.jag_index16 == 1
+    assert o.index16 == 1
     assert ctypes.sizeof(o) == 104
     assert B.status_string(B.E_ZERO_FDIAG) == "MGR_E_ZERO_FDIAG"
     assert B.status_string(B.NOT_CONVERGED) == "MGR_NOT_CONVERGED"

@@ -281,8 +281,10 @@ def test_kernel_timing_counts_and_bytes():
     # application; kernel 2: the sweeps on the coarse-grid matrix, launched on
     # their own when it is larger than the single-workgroup tail takes (1,600
     # rows here; the levels below it run in the tail kernel)
+    # (32-bit columns in the sliced ELL: the byte model below; the 16-bit form is
+    # checked at the end)
     s = small_system((40, 40), seed=5, sigma=1.0, frac=0.4)
-    g = gpu_solver(s)
+    g = gpu_solver(s, index16=0)
     g.set_kernel_timing(True)
     x, info = g.solve(s.b, 1e-8)
     ms0, n0, b0 = g.kernel_time(0)
@@ -309,6 +311,15 @@ def test_kernel_timing_counts_and_bytes():
     with pytest.raises(Exception):
         g.kernel_time(3)
     g.close()
+    # 16-bit columns in the sliced ELL: 2 bytes less per entry, 4 more per slot
+    # of 64 (a slot's base)
+    g = gpu_solver(s, index16=1)
+    g.set_kernel_timing(True)
+    g.solve(s.b, 1e-8)
+    _, n16, b16 = g.kernel_time(0)
+    g.close()
+    assert n16 == n0
+    assert 1.5 * nnz < per0 - b16 / n16 <= 2 * nnz, (per0, b16 / n16, nnz)
 
 
 def test_reused_device_blocks_give_the_same_bits():
