@@ -46,6 +46,9 @@ __device__ inline int64_t xcd_grouped_block() {
 // Mode 5 (y = e_F + A x, the prolongation that also writes the F-relaxation's
 // correction, kept compact by F index, with zeros on the C points): r holds the
 // compact correction and d carries the int32 F index map (-1 on C points).
+// Mode 6: the same value added into the finer level's vector, y[m[row]] +=
+// (e_F + A x), with the int32 map m carried by y2 (the W_p = 0 prolongation of
+// the finer level done by this level's last launch).
 template <typename T, int MODE>
 struct RowIn {
     T a = 0, b = 0, c = 0;
@@ -53,7 +56,7 @@ struct RowIn {
                                 const T *__restrict__ d, const T *__restrict__ y) {
         if (MODE == 1) a = r[row];
         if (MODE == 2) a = y[row];
-        if (MODE == 5) {
+        if (MODE == 5 || MODE == 6) {
             const int f = reinterpret_cast<const int32_t *>(d)[row];
             a = f >= 0 ? r[f] : (T)0;
         }
@@ -67,6 +70,11 @@ struct RowIn {
         if (MODE == 0) y[row] = acc;
         else if (MODE == 1) y[row] = a - acc;
         else if (MODE == 2 || MODE == 5) y[row] = a + acc;
+        else if (MODE == 6) {
+            const int64_t j = reinterpret_cast<const int32_t *>(y2)[row];
+            const T v = a + acc;
+            y[j] = y[j] + v;
+        }
         else if (MODE == 3) y[row] = a + (b - acc) / c;
         else {
             y[row] = acc;
@@ -810,7 +818,8 @@ static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T
     case 2: MGR_STREAM(2); break;
     case 3: MGR_STREAM(3); break;
     case 4: MGR_STREAM(4); break;
-    default: MGR_STREAM(5); break;
+    case 5: MGR_STREAM(5); break;
+    default: MGR_STREAM(6); break;
     }
 #undef MGR_STREAM
 }
@@ -841,7 +850,8 @@ static void jag_rows(int mode, const DCsr &A, const T *x, const T *r, const T *d
     case 2: MGR_JAG(IX, LDSN, 2, CI); break;        \
     case 3: MGR_JAG(IX, LDSN, 3, CI); break;        \
     case 4: MGR_JAG(IX, LDSN, 4, CI); break;        \
-    default: MGR_JAG(IX, LDSN, 5, CI); break;       \
+    case 5: MGR_JAG(IX, LDSN, 5, CI); break;        \
+    default: MGR_JAG(IX, LDSN, 6, CI); break;       \
     }
     if (J.co) {
         MGR_JAG_MODES(uint16_t, 4096, J.co)
@@ -914,7 +924,8 @@ static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T 
     case 2: csr_lanes<T, 2>(A, lanes, vals, x, r, d, y, y2, s); break;
     case 3: csr_lanes<T, 3>(A, lanes, vals, x, r, d, y, y2, s); break;
     case 4: csr_lanes<T, 4>(A, lanes, vals, x, r, d, y, y2, s); break;
-    default: csr_lanes<T, 5>(A, lanes, vals, x, r, d, y, y2, s); break;
+    case 5: csr_lanes<T, 5>(A, lanes, vals, x, r, d, y, y2, s); break;
+    default: csr_lanes<T, 6>(A, lanes, vals, x, r, d, y, y2, s); break;
     }
 }
 
@@ -941,6 +952,13 @@ void launch_amg_tail(const TailDesc<T> &d, hipStream_t s) {
 template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
     csr_any<T>(mode, A, vals, x, r, d, y, nullptr, s);
+}
+
+template <typename T>
+void launch_csr_prolong_into(const DCsr &A, const T *vals, const T *x, const T *eF, const int32_t *fmap,
+                             const int32_t *map, T *y, hipStream_t s) {
+    csr_any<T>(6, A, vals, x, eF, reinterpret_cast<const T *>(fmap), y,
+               reinterpret_cast<T *>(const_cast<int32_t *>(map)), s);
 }
 
 template <typename T>
@@ -1060,6 +1078,8 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
     template void launch_amg_tail<T>(const TailDesc<T> &, hipStream_t);                                       \
     template void launch_csr<T>(int, const DCsr &, const T *, const T *, const T *, const T *, T *, hipStream_t); \
     template void launch_csr_restrict_div<T>(const DCsr &, const T *, const T *, const T *, T *, T *, hipStream_t); \
+    template void launch_csr_prolong_into<T>(const DCsr &, const T *, const T *, const T *, const int32_t *,     \
+                                             const int32_t *, T *, hipStream_t);                                \
     template void launch_csr_rows_residual<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *, \
                                               const T *, T *, hipStream_t);                                     \
     template void launch_frelax_inplace<T>(const DCsr &, int, const T *, int64_t, const int32_t *, const T *,   \

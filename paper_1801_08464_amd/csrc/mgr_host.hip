@@ -1033,8 +1033,18 @@ struct Io64 {
     double *out = nullptr;
 };
 
+// Where the finer level's prolongation is e_C += e_c (W_p = 0), that level may
+// hand its vector and C list down: the coarser level then adds its result into
+// dst[map[i]] instead of writing e (its last launch does both).
 template <typename T>
-void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, const Io64 *io = nullptr) {
+struct OutMap {
+    const int32_t *map = nullptr;
+    T *dst = nullptr;
+};
+
+template <typename T>
+void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, const Io64 *io = nullptr,
+               const OutMap<T> *om = nullptr) {
     if (l == h->L) {
         amg_cycle<T>(h, h->cg, 0, r, e, x0_ready);
         return;
@@ -1057,7 +1067,7 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, co
     }
     // restriction rc = R src, then the next level's cycle; into the coarse grid the
     // restriction also writes the AMG cycle's first Jacobi iterate rc / l1
-    auto coarse_correction = [&](const T *src) {
+    auto coarse_correction = [&](const T *src, const OutMap<T> *into = nullptr) {
         if (l + 1 == h->L && amg_takes_x0<T>(h->cg)) {
             AmgLevel &c0 = h->cg.lev[0];
             launch_csr_restrict_div<T>(lv.R, P_<T>::v(lv.R), src, P_<T>::l1(c0), rc, amg_x0_buffer<T>(h->cg, 0, ec),
@@ -1066,7 +1076,7 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, co
             mgr_cycle<T>(h, l + 1, rc, ec, true);
         } else {
             csr<T>(h, 0, lv.R, P_<T>::v(lv.R), src, nullptr, nullptr, rc);
-            mgr_cycle<T>(h, l + 1, rc, ec);
+            mgr_cycle<T>(h, l + 1, rc, ec, false, nullptr, into);
         }
     };
     // F-relaxation sweeps: Jacobi with diag(A_FF), or one AMG V-cycle on A_FF;
@@ -1145,6 +1155,13 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, co
         launch_csr<T>(1, lv.AcF, P_<T>::v(lv.AcF), eF, r, nullptr, t, s);
         acct(h, csr_bytes(lv.AcF, 1, S));
         coarse_correction(t);
+        if (om && lv.P.nnz != lv.nC) {
+            // e is not kept: the result goes straight into the finer level's vector
+            launch_csr_prolong_into<T>(lv.P, P_<T>::v(lv.P), ec, eF, lv.fmap, om->map, om->dst, s);
+            // mode 5's count, the map, and the finer vector read where it is updated
+            acct(h, csr_bytes(lv.P, 0, S) + 4.0 * n + S * nF + 4.0 * n + S * n);
+            return;
+        }
         if (lv.P.nnz == lv.nC) {
             launch_prolong_inject_compact<T>(lv.n, lv.fmap, lv.cmap, eF, ec, e, s);
             acct(h, 8.0 * n + S * nF + S * (double)lv.nC + S * n);
@@ -1152,6 +1169,10 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, co
             launch_csr<T>(5, lv.P, P_<T>::v(lv.P), ec, eF, reinterpret_cast<const T *>(lv.fmap), e, s);
             // the gathered e_c and the written e (mode 0's count), the F map and e_F
             acct(h, csr_bytes(lv.P, 0, S) + 4.0 * n + S * nF);
+        }
+        if (om) {
+            launch_scatter_add<T>(lv.n, om->map, e, om->dst, s);
+            acct(h, 4.0 * n + 3.0 * S * n);
         }
         return;
     }
@@ -1197,6 +1218,14 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, co
     if (lv.AcF.v && !global) csr<T>(h, 1, lv.AcF, P_<T>::v(lv.AcF), e, r, nullptr, t);
     else if (l == 0) fine_op<T>(h, 1, e, r, t);
     else csr<T>(h, 1, lv.A, Av, e, r, nullptr, t);
+    if (lv.P.nnz == lv.nC && l + 1 < h->L && h->lev[l + 1].fcompact && !io && !om) {
+        // e_C += e_c done by the next level's last launch, into e through the C list
+        OutMap<T> into;
+        into.map = lv.clist;
+        into.dst = e;
+        coarse_correction(t, &into);
+        return;
+    }
     coarse_correction(t);
     if constexpr (std::is_same<T, float>::value) {
         if (io && lv.P.nnz == lv.nC) {
@@ -1219,6 +1248,11 @@ void mgr_cycle(mgr_handle *h, int l, const T *r, T *e, bool x0_ready = false, co
             launch_cast_f32_f64(e, io->out, lv.n, s);
             acct(h, 12.0 * n);
         }
+    }
+    if (om) {
+        // (not reached by the cycles built here: only compact levels get a map)
+        launch_scatter_add<T>(lv.n, om->map, e, om->dst, s);
+        acct(h, 4.0 * n + 3.0 * S * n);
     }
 }
 

@@ -329,6 +329,11 @@ void launch_jag_count(const DCsr &A, int32_t *cnt, hipStream_t s);
 void launch_jag_fill(const DCsr &A, Jag &J, int *bad, hipStream_t s);
 template <typename T>
 void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s);
+// y[map[i]] += eF[fmap[i]] (0 where fmap[i] < 0) + (A x)[i]: a level's prolongation
+// with its compact F correction, added into the finer level's vector through map
+template <typename T>
+void launch_csr_prolong_into(const DCsr &A, const T *vals, const T *x, const T *eF, const int32_t *fmap,
+                             const int32_t *map, T *y, hipStream_t s);
 // y = A x and y2 = y / d (restriction that also starts the next level's Jacobi sweeps)
 template <typename T>
 void launch_csr_restrict_div(const DCsr &A, const T *vals, const T *x, const T *d, T *y, T *y2, hipStream_t s);
