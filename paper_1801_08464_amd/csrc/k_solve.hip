@@ -883,8 +883,11 @@ static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const
 // (64 rows of >= 24 entries, 128 rows of >= 12), which issues a level's loads
 // in one wave of workgroups (AMG level 2 of the 128^3 coarse grid, 123 k rows of
 // 38 entries: 25 -> 17 us per sweep against the lanes kernel); smaller levels
-// take the lanes-per-row kernel, whose launches are latency-bound anyway.
-constexpr int64_t kCsrStreamMinRows = 131072;
+// take the lanes-per-row kernel, whose launches are latency-bound anyway.  The
+// cut sits where 256-row blocks fill a wave of resident workgroups about once
+// (the F-block AMG's level 2, 142 k rows, left the jagged kernel's 554 blocks:
+// V-cycle -9 us).
+constexpr int64_t kCsrStreamMinRows = 262144;
 constexpr int64_t kCsrStreamSmallRows = 8192;
 // mean row lengths below which the stream kernel takes 1024- and 2048-entry passes
 // (above: 5120 entries in FP64, 20 per thread, 40 KB of LDS: 4 workgroups per CU;
