@@ -884,10 +884,13 @@ static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const
 // in one wave of workgroups (AMG level 2 of the 128^3 coarse grid, 123 k rows of
 // 38 entries: 25 -> 17 us per sweep against the lanes kernel); smaller levels
 // take the lanes-per-row kernel, whose launches are latency-bound anyway.  The
-// cut sits where 256-row blocks fill a wave of resident workgroups about once
-// (the F-block AMG's level 2, 142 k rows, left the jagged kernel's 554 blocks:
-// V-cycle -9 us).
-constexpr int64_t kCsrStreamMinRows = 262144;
+// cut, at 1 M rows, gives the long-row levels of 0.1-1 M rows (the AMG level 1
+// of the 128^3 coarse grid, 0.70 M rows of 34 entries, and the F-block AMG's
+// levels 1 and 2) the smaller blocks: their 256-row grids (the jagged copies
+// included) filled 0.5-2.7 waves of resident workgroups; V-cycle -34 us.  The
+// coarse grid itself (2.1 M rows) keeps the jagged kernel (128-row stream
+// blocks: 148 against 138 us per sweep).
+constexpr int64_t kCsrStreamMinRows = 1048576;
 constexpr int64_t kCsrStreamSmallRows = 8192;
 // mean row lengths below which the stream kernel takes 1024- and 2048-entry passes
 // (above: 5120 entries in FP64, 20 per thread, 40 KB of LDS: 4 workgroups per CU;

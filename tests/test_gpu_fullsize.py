@@ -110,6 +110,45 @@ def test_cfg4_level2_fblock_has_no_strong_connections(orc, cfg4):
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_solve_cfg4.json")
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cfg4_column_forms_bitwise(cfg4, precision):
+    """The solve-phase copies with 16-bit column offsets (the default: the
+    level-0 operator's sliced ELL, and in the mixed-precision hierarchy the
+    coarse-grid matrix's jagged copy) and with 32-bit columns give the same
+    V-cycle and the same solve, bit for bit: config 4's coarse-grid matrix
+    (2,097,152 rows, 24 entries per row) takes the jagged copy.  The FP64
+    hierarchy's jagged copies keep 32-bit columns either way."""
+    import torch
+    from paper_1801_08464_amd.solver import MGRSolver
+    s, _ = cfg4
+    r = random_vector(s.n, 43)
+    out = {}
+    for c16 in (1, 0):
+        print(f"[config 4 {precision}] index16={c16}", flush=True)
+        g = MGRSolver(s.indptr, s.indices, s.data, s.labels, precision=precision, index16=c16, **SOLVER_OPTS)
+        g.set_kernel_timing(True)
+        z = g.apply_preconditioner(r).cpu().numpy()
+        _, sweeps, sweep_bytes = g.kernel_time(2)
+        _, fines, fine_bytes = g.kernel_time(0)
+        g.set_kernel_timing(False)
+        x, info = g.solve(s.b, 1e-8)
+        out[c16] = (z, x.cpu().numpy(), info.iterations, sweep_bytes / sweeps, info.level_nnz[3], fine_bytes / fines)
+        g.close()
+        torch.cuda.synchronize()
+    # the coarse-grid sweeps read 2 bytes less per entry in the 16-bit form (and
+    # 4 more per slot-table entry): the form was taken where it applies
+    nnz3 = out[1][4]  # the coarse grid A_3 follows the three MGR levels
+    if precision == "mixed":
+        assert out[0][3] - out[1][3] > 1.9 * nnz3, (out[0][3], out[1][3], nnz3)
+    else:
+        assert out[0][3] == out[1][3], (out[0][3], out[1][3])
+    # and so does the level-0 operator (the V-cycle's level-0 residual)
+    assert out[0][5] - out[1][5] > 1.9 * s.nnz, (out[0][5], out[1][5], s.nnz)
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][2] == out[1][2]
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 @pytest.fixture(scope="module")
 def golden4():
     with open(GOLDEN) as f:
