@@ -326,6 +326,28 @@ VARIANTS = {
 }
 
 
+def run_size_scaling(dev, configs, tol, forms_cfg, big_cfg):
+    """Iterations and unknowns/s against problem size (the workloads of configs
+    1-3, beside the main config's forms): each config's FP64 and mixed step with
+    the benchmark's options, 2 timed steps after 1 warm-up."""
+    from synth import CONFIGS, make_config
+    rows = []
+    for cfg in configs:
+        s = make_config(cfg)
+        for form in ("fp64", "mixed"):
+            r = run_form(s, dev, form, 2, 1, tol)
+            rows.append(dict(config=cfg, grid="x".join(map(str, CONFIGS[cfg]["grid"])), unknowns=s.n, form=form,
+                             iterations=r["iterations"], ms_per_step=r["ms_per_step"], setup_ms=r["setup_ms"],
+                             solve_ms=r["solve_ms"], unknowns_per_s=r["unknowns_per_s"]))
+        del s
+    for form in ("fp64", "mixed"):
+        r = forms_cfg[form]
+        rows.append(dict(config=big_cfg, grid="x".join(map(str, CONFIGS[big_cfg]["grid"])), unknowns=None, form=form,
+                         iterations=r["iterations"], ms_per_step=r["ms_per_step"], setup_ms=r["setup_ms"],
+                         solve_ms=r["solve_ms"], unknowns_per_s=r["unknowns_per_s"]))
+    return rows
+
+
 def run_variants(dev, configs, tol, warmup):
     import torch
 
@@ -459,6 +481,11 @@ def main():
                        for k, v in forms.items() if "vcycle" in v and k not in ("adjoint", "newton")},
         "forms": forms,
     }
+    if "fp64" in forms and "mixed" in forms and args.config == 4:
+        line["size_scaling"] = run_size_scaling(dev, (1, 2, 3), args.tol, forms, args.config)
+        for r in line["size_scaling"]:
+            if r["unknowns"] is None:
+                r["unknowns"] = s.n
     if oracle_run is not None:
         log("waiting for the oracle ...")
         orc = finish_oracle_jobs(*oracle_run)
