@@ -253,6 +253,51 @@ def test_validation_covers_every_row_of_a_large_input():
     assert e.value.code == B.E_INVALID
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_index16_falls_back_where_a_slot_spans_too_far(precision):
+    # a 29^3 system (73,167 rows) in which the pressure row of cell 24,256 (the
+    # first cell of a full 64-cell slice) also couples to the pressure of cell 0:
+    # that slice's first pressure slot then holds column 0 beside columns above
+    # 70,000, a span no 16-bit offset reaches, so the fine operator keeps 32-bit
+    # columns (the same bytes per launch as with index16 = 0) and every result is
+    # bitwise that of the 32-bit form
+    import dataclasses
+    import scipy.sparse as sp
+    s = small_system((29, 29, 29), seed=9, sigma=1.5, frac=0.3, region="ball")
+    # the unmodified system packs 16-bit columns
+    g = gpu_solver(s, precision=precision, index16=1)
+    g.set_kernel_timing(True)
+    g.spmv(random_vector(s.n, 17))
+    _, n_plain, b_plain = g.kernel_time(0)
+    g.close()
+    i = 3 * 24256
+    A = sp.csr_matrix((s.data, s.indices, s.indptr), shape=(s.n, s.n))
+    assert A.indices[A.indptr[i]] > 65535 + 3 * 64
+    eps = 1e-3 * A[i, i]
+    A = (A + sp.csr_matrix(([-eps, eps], ([i, i], [0, i])), shape=A.shape)).tocsr()
+    A.sort_indices()
+    assert A.indices[A.indptr[i]] == 0
+    s = dataclasses.replace(s, indptr=A.indptr.astype(np.int32), indices=A.indices.astype(np.int32),
+                            data=np.ascontiguousarray(A.data, dtype=np.float64))
+    r = random_vector(s.n, 17)
+    out = {}
+    for c16 in (1, 0):
+        print(f"[index16 fallback] {precision} index16={c16} n={s.n}", flush=True)
+        g = gpu_solver(s, precision=precision, index16=c16)
+        g.set_kernel_timing(True)
+        z = g.apply_preconditioner(r).cpu().numpy()
+        _, nz, bz = g.kernel_time(0)
+        y = g.spmv(r).cpu().numpy()
+        _, ny, by = g.kernel_time(0)
+        g.close()
+        assert nz > 0 and ny == 1
+        out[c16] = (z, y, bz / nz, by)
+    assert n_plain == 1 and b_plain < out[0][3] - 1.5 * len(s.data), (b_plain, out[0][3])
+    assert out[1][2:] == out[0][2:], (out[1][2:], out[0][2:])
+    assert np.array_equal(out[1][0], out[0][0])
+    assert np.array_equal(out[1][1], out[0][1])
+
+
 def test_empty_system_is_rejected():
     # n = 0: the setup refuses it (no partial handle is returned)
     from paper_1801_08464_amd import binding as B
