@@ -206,7 +206,10 @@ int mgr_get_vector(mgr_handle *h, int kind, int level, void *out, int64_t *len);
  * residual kernel, every l1-Jacobi sweep on the coarse-grid matrix (level 0 of
  * the coarse AMG hierarchy), and every whole preconditioner application (the MGR
  * V-cycle of Section 4, algorithm "MGR preconditioner with presmoothing", inside mgr_solve or
- * mgr_apply_preconditioner), is bracketed by HIP events on the handle's stream.
+ * mgr_apply_preconditioner), is timed by HIP events on the handle's stream: the
+ * two kernels' launches record their own start and end events
+ * (hipExtLaunchKernelGGL), so each interval is the kernel's execution alone;
+ * an application is bracketed by events recorded before and after it.
  * mgr_kernel_time (synchronises) returns the summed event time, the number of
  * launches and the summed algorithmic bytes of those launches, then resets the
  * counters.  kernel: 0 = the level-0 kernel (bytes: stored values and column

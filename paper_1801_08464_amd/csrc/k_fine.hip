@@ -80,11 +80,18 @@ __global__ void __launch_bounds__(256) k_csell(int64_t ncell, int64_t nslice, co
 constexpr int BT = 256;
 
 template <typename T>
-void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s) {
+void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s,
+                  KEvents ev) {
     if (A.nslice <= 0) return;
     const unsigned g = nblocks(A.nslice, BT / kWave);
-#define MGR_CSELL_M(IX, CI, M, BS) \
-    k_csell<T, IX, M, BS><<<g, BT, 0, s>>>(A.ncell, A.nslice, A.off, A.width, CI, A.sb, vals, x, r, y)
+#define MGR_CSELL_M(IX, CI, M, BS)                                                                            \
+    do {                                                                                                      \
+        if (ev.start)                                                                                         \
+            hipExtLaunchKernelGGL(k_csell<T, IX, M, BS>, dim3(g), dim3(BT), 0, s, ev.start, ev.stop, 0, A.ncell, \
+                                  A.nslice, A.off, A.width, CI, A.sb, vals, x, r, y);                         \
+        else                                                                                                  \
+            k_csell<T, IX, M, BS><<<g, BT, 0, s>>>(A.ncell, A.nslice, A.off, A.width, CI, A.sb, vals, x, r, y); \
+    } while (0)
 #define MGR_CSELL(IX, CI, BS)                            \
     do {                                                 \
         if (mode == 0) MGR_CSELL_M(IX, CI, 0, BS);       \
@@ -103,8 +110,8 @@ void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *
 }
 
 template void launch_csell<double>(int, const CSell &, const double *, const double *, const double *, double *,
-                                   hipStream_t);
+                                   hipStream_t, KEvents);
 template void launch_csell<float>(int, const CSell &, const float *, const float *, const float *, float *,
-                                  hipStream_t);
+                                  hipStream_t, KEvents);
 
 }  // namespace mgr

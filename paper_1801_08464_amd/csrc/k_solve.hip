@@ -809,9 +809,16 @@ constexpr int BT = 256;
 
 template <typename T, int ROWS, int NT, int LDSN>
 static void csr_rows(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
-                     hipStream_t s) {
+                     hipStream_t s, KEvents ev) {
     const unsigned g = nblocks(A.nrows, ROWS);
-#define MGR_STREAM(M) k_csr_stream<T, M, ROWS, NT, LDSN><<<g, NT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2)
+#define MGR_STREAM(M)                                                                                               \
+    do {                                                                                                            \
+        if (ev.start)                                                                                               \
+            hipExtLaunchKernelGGL(k_csr_stream<T, M, ROWS, NT, LDSN>, dim3(g), dim3(NT), 0, s, ev.start, ev.stop, 0, \
+                                  A.nrows, A.rp, A.ci, vals, x, r, d, y, y2);                                       \
+        else                                                                                                        \
+            k_csr_stream<T, M, ROWS, NT, LDSN><<<g, NT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2);         \
+    } while (0)
     switch (mode) {
     case 0: MGR_STREAM(0); break;
     case 1: MGR_STREAM(1); break;
@@ -832,7 +839,8 @@ template <>
 const float *jag_vals<float>(const Jag &J) { return J.vf; }
 
 template <typename T>
-static void jag_rows(int mode, const DCsr &A, const T *x, const T *r, const T *d, T *y, T *y2, hipStream_t s) {
+static void jag_rows(int mode, const DCsr &A, const T *x, const T *r, const T *d, T *y, T *y2, hipStream_t s,
+                     KEvents ev) {
     const Jag &J = *A.jag;
     const unsigned g = (unsigned)J.nblk;
     // passes of 4864 FP64 entries (19 per thread): with the 2 KB slot table the
@@ -840,9 +848,15 @@ static void jag_rows(int mode, const DCsr &A, const T *x, const T *r, const T *d
     // on the coarse-grid sweep); 4096 with the 16-bit columns' second 2 KB table
     // (slot bases).  FP32 8192, and 4096 with the 16-bit columns (whose slot
     // bases take 32 more registers at 8192: three waves per SIMD, sweep +60 %)
-#define MGR_JAG(IX, LDSN, M, CI)                                                                                  \
-    k_jag_stream<T, IX, M, LDSN><<<g, kJagRows, 0, s>>>(A.nrows, A.rp, CI, J.sb, jag_vals<T>(J), J.rows, J.bst, J.st, \
-                                                        x, r, d, y, y2)
+#define MGR_JAG(IX, LDSN, M, CI)                                                                                   \
+    do {                                                                                                           \
+        if (ev.start)                                                                                              \
+            hipExtLaunchKernelGGL(k_jag_stream<T, IX, M, LDSN>, dim3(g), dim3(kJagRows), 0, s, ev.start, ev.stop, 0, \
+                                  A.nrows, A.rp, CI, J.sb, jag_vals<T>(J), J.rows, J.bst, J.st, x, r, d, y, y2);   \
+        else                                                                                                       \
+            k_jag_stream<T, IX, M, LDSN><<<g, kJagRows, 0, s>>>(A.nrows, A.rp, CI, J.sb, jag_vals<T>(J), J.rows,   \
+                                                                J.bst, J.st, x, r, d, y, y2);                     \
+    } while (0)
 #define MGR_JAG_MODES(IX, LDSN, CI)                 \
     switch (mode) {                                 \
     case 0: MGR_JAG(IX, LDSN, 0, CI); break;        \
@@ -864,9 +878,16 @@ static void jag_rows(int mode, const DCsr &A, const T *x, const T *r, const T *d
 
 template <typename T, int MODE>
 static void csr_lanes(const DCsr &A, int lanes, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
-                      hipStream_t s) {
+                      hipStream_t s, KEvents ev) {
     const unsigned g = nblocks(A.nrows * lanes, BT);
-#define MGR_LANES(L) k_csr_lanes<T, MODE, L><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2)
+#define MGR_LANES(L)                                                                                                 \
+    do {                                                                                                             \
+        if (ev.start)                                                                                                \
+            hipExtLaunchKernelGGL(k_csr_lanes<T, MODE, L>, dim3(g), dim3(BT), 0, s, ev.start, ev.stop, 0, A.nrows,   \
+                                  A.rp, A.ci, vals, x, r, d, y, y2);                                                 \
+        else                                                                                                         \
+            k_csr_lanes<T, MODE, L><<<g, BT, 0, s>>>(A.nrows, A.rp, A.ci, vals, x, r, d, y, y2);                     \
+    } while (0)
     switch (lanes) {
     case 2: MGR_LANES(2); break;
     case 4: MGR_LANES(4); break;
@@ -903,35 +924,35 @@ constexpr double kStreamMidRow = 8.0;
 // sequential row sums).  Small levels: several lanes per row.
 template <typename T>
 static void csr_any(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, T *y2,
-                    hipStream_t s) {
+                    hipStream_t s, KEvents ev = {}) {
     if (A.nrows <= 0) return;
     const double avg = (double)A.nnz / (double)A.nrows;
     if (A.nrows >= kCsrStreamMinRows) {
         if (A.jag && avg >= kStreamMidRow) {
-            jag_rows<T>(mode, A, x, r, d, y, y2, s);
+            jag_rows<T>(mode, A, x, r, d, y, y2, s, ev);
             return;
         }
-        if (avg < kStreamShortRow) csr_rows<T, 256, 256, 1024>(mode, A, vals, x, r, d, y, y2, s);
-        else if (avg < kStreamMidRow) csr_rows<T, 256, 256, 2048>(mode, A, vals, x, r, d, y, y2, s);
-        else if (sizeof(T) == 4) csr_rows<T, 256, 256, 8192>(mode, A, vals, x, r, d, y, y2, s);
-        else csr_rows<T, 256, 256, 5120>(mode, A, vals, x, r, d, y, y2, s);
+        if (avg < kStreamShortRow) csr_rows<T, 256, 256, 1024>(mode, A, vals, x, r, d, y, y2, s, ev);
+        else if (avg < kStreamMidRow) csr_rows<T, 256, 256, 2048>(mode, A, vals, x, r, d, y, y2, s, ev);
+        else if (sizeof(T) == 4) csr_rows<T, 256, 256, 8192>(mode, A, vals, x, r, d, y, y2, s, ev);
+        else csr_rows<T, 256, 256, 5120>(mode, A, vals, x, r, d, y, y2, s, ev);
         return;
     }
     if (A.nrows >= kCsrStreamSmallRows) {
-        if (avg >= 24) csr_rows<T, 64, 256, 4864>(mode, A, vals, x, r, d, y, y2, s);
-        else if (avg >= 12) csr_rows<T, 128, 256, 4864>(mode, A, vals, x, r, d, y, y2, s);
-        else csr_rows<T, 256, 256, 2048>(mode, A, vals, x, r, d, y, y2, s);
+        if (avg >= 24) csr_rows<T, 64, 256, 4864>(mode, A, vals, x, r, d, y, y2, s, ev);
+        else if (avg >= 12) csr_rows<T, 128, 256, 4864>(mode, A, vals, x, r, d, y, y2, s, ev);
+        else csr_rows<T, 256, 256, 2048>(mode, A, vals, x, r, d, y, y2, s, ev);
         return;
     }
     const int lanes = avg < 3 ? 2 : avg < 6 ? 4 : avg < 12 ? 8 : avg < 24 ? 16 : 32;
     switch (mode) {
-    case 0: csr_lanes<T, 0>(A, lanes, vals, x, r, d, y, y2, s); break;
-    case 1: csr_lanes<T, 1>(A, lanes, vals, x, r, d, y, y2, s); break;
-    case 2: csr_lanes<T, 2>(A, lanes, vals, x, r, d, y, y2, s); break;
-    case 3: csr_lanes<T, 3>(A, lanes, vals, x, r, d, y, y2, s); break;
-    case 4: csr_lanes<T, 4>(A, lanes, vals, x, r, d, y, y2, s); break;
-    case 5: csr_lanes<T, 5>(A, lanes, vals, x, r, d, y, y2, s); break;
-    default: csr_lanes<T, 6>(A, lanes, vals, x, r, d, y, y2, s); break;
+    case 0: csr_lanes<T, 0>(A, lanes, vals, x, r, d, y, y2, s, ev); break;
+    case 1: csr_lanes<T, 1>(A, lanes, vals, x, r, d, y, y2, s, ev); break;
+    case 2: csr_lanes<T, 2>(A, lanes, vals, x, r, d, y, y2, s, ev); break;
+    case 3: csr_lanes<T, 3>(A, lanes, vals, x, r, d, y, y2, s, ev); break;
+    case 4: csr_lanes<T, 4>(A, lanes, vals, x, r, d, y, y2, s, ev); break;
+    case 5: csr_lanes<T, 5>(A, lanes, vals, x, r, d, y, y2, s, ev); break;
+    default: csr_lanes<T, 6>(A, lanes, vals, x, r, d, y, y2, s, ev); break;
     }
 }
 
@@ -956,8 +977,9 @@ void launch_amg_tail(const TailDesc<T> &d, hipStream_t s) {
 }
 
 template <typename T>
-void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s) {
-    csr_any<T>(mode, A, vals, x, r, d, y, nullptr, s);
+void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s,
+                KEvents ev) {
+    csr_any<T>(mode, A, vals, x, r, d, y, nullptr, s, ev);
 }
 
 template <typename T>
@@ -1082,7 +1104,8 @@ void launch_lu_solve(int64_t n, const double *lu, const int32_t *perm, const T *
 
 #define MGR_INSTANTIATE(T)                                                                                      \
     template void launch_amg_tail<T>(const TailDesc<T> &, hipStream_t);                                       \
-    template void launch_csr<T>(int, const DCsr &, const T *, const T *, const T *, const T *, T *, hipStream_t); \
+    template void launch_csr<T>(int, const DCsr &, const T *, const T *, const T *, const T *, T *, hipStream_t,    \
+                                KEvents);                                                                           \
     template void launch_csr_restrict_div<T>(const DCsr &, const T *, const T *, const T *, T *, T *, hipStream_t); \
     template void launch_csr_prolong_into<T>(const DCsr &, const T *, const T *, const T *, const int32_t *,     \
                                              const int32_t *, T *, hipStream_t);                                \

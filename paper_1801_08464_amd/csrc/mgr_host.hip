@@ -839,15 +839,28 @@ struct P_<float> {
 // Algorithmic bytes count every array a launch reads or writes once: stored
 // values and column indices, row pointers, the gathered vector at its length,
 // and each dense vector the launch touches.
-hipEvent_t timer_mark(mgr_handle *h, mgr_handle::Timer &t) {
+hipEvent_t timer_event(mgr_handle *h, mgr_handle::Timer &t) {
     if (t.ev.size() <= t.used) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         t.ev.push_back(e);
     }
-    hipEvent_t e = t.ev[t.used++];
+    return t.ev[t.used++];
+}
+
+hipEvent_t timer_mark(mgr_handle *h, mgr_handle::Timer &t) {
+    hipEvent_t e = timer_event(h, t);
     HIPCHK(hipEventRecord(e, h->stream));
     return e;
+}
+
+// the next event pair of t, for a launch that records them itself (a single
+// kernel: the pair then holds its own start and end)
+KEvents timer_kernel(mgr_handle *h, mgr_handle::Timer &t) {
+    KEvents ev;
+    ev.start = timer_event(h, t);
+    ev.stop = timer_event(h, t);
+    return ev;
 }
 
 inline void acct(mgr_handle *h, double bytes) {
@@ -869,13 +882,13 @@ double csr_bytes(const DCsr &A, int mode, double S) {
     return b;
 }
 
-// the fine-level sliced-ELL kernel, optionally bracketed by events for timing
+// the fine-level sliced-ELL kernel, timed by its own start and end events when
+// timing is on
 template <typename T>
 void fine_op(mgr_handle *h, int mode, const T *x, const T *r, T *y) {
-    if (h->timing) timer_mark(h, h->tm[0]);
-    launch_csell<T>(mode, h->A0s, P_<T>::v(h->A0s), x, r, y, h->stream);
+    launch_csell<T>(mode, h->A0s, P_<T>::v(h->A0s), x, r, y, h->stream,
+                    h->timing ? timer_kernel(h, h->tm[0]) : KEvents{});
     if (h->timing) {
-        timer_mark(h, h->tm[0]);
         // values + columns of the true nonzeros, row pointers, x and y, plus r
         // for the residual form
         const double n = (double)h->n;
@@ -891,21 +904,21 @@ void fine_op(mgr_handle *h, int mode, const T *x, const T *r, T *y) {
 }
 
 template <typename T>
-void csr(mgr_handle *h, int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y) {
-    launch_csr<T>(mode, A, vals, x, r, d, y, h->stream);
+void csr(mgr_handle *h, int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y,
+         KEvents ev = {}) {
+    launch_csr<T>(mode, A, vals, x, r, d, y, h->stream, ev);
     acct(h, csr_bytes(A, mode, sizeof(T)));
 }
 
 // a Jacobi sweep on level k of hierarchy H; the sweeps on the coarse-grid matrix
-// itself (level 0 of the coarse hierarchy) are bracketed by events when timing
+// itself (level 0 of the coarse hierarchy) are timed by their own start and end
+// events when timing is on
 template <typename T>
 void sweep(mgr_handle *h, const AmgHier &H, int k, const DCsr &A, const T *vals, const T *x, const T *r,
            const T *d, T *y) {
     const bool timed = h->timing && &H == &h->cg && k == 0;
-    if (timed) timer_mark(h, h->tm[2]);
-    csr<T>(h, 3, A, vals, x, r, d, y);
+    csr<T>(h, 3, A, vals, x, r, d, y, timed ? timer_kernel(h, h->tm[2]) : KEvents{});
     if (timed) {
-        timer_mark(h, h->tm[2]);
         h->tm[2].bytes += csr_bytes(A, 3, sizeof(T));
         h->tm[2].launches++;
     }

@@ -1,5 +1,6 @@
 // Internal declarations of libmgr (HIP, gfx950).  Not part of the C ABI.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -204,7 +205,9 @@ struct mgr_handle {
 
     // event timing (mgr_set_kernel_timing): tm[0] the level-0 sliced-ELL kernel,
     // tm[1] whole preconditioner applications (the V-cycle), tm[2] the l1-Jacobi
-    // sweeps on the coarse-grid matrix (level 0 of the coarse AMG hierarchy)
+    // sweeps on the coarse-grid matrix (level 0 of the coarse AMG hierarchy).
+    // tm[0] and tm[2] hold each launch's own start and end (events the launch
+    // records); tm[1] events recorded on the stream around each application
     struct Timer {
         std::vector<hipEvent_t> ev;
         size_t used = 0;
@@ -315,8 +318,15 @@ void launch_pattern_outer(int64_t n, const int32_t *rp, const int32_t *ci, const
                           double *d, hipStream_t s);
 
 // ---- solve-phase kernels (k_solve.hip) ----
+// Events that a timed launch records itself (hipExtLaunchKernelGGL): they then
+// hold the kernel's own start and end, the interval a kernel trace reports,
+// rather than the queue around it.  Null: a plain launch.
+struct KEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
 template <typename T>
-void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s);
+void launch_csell(int mode, const CSell &A, const T *vals, const T *x, const T *r, T *y, hipStream_t s,
+                  KEvents ev = {});
 // mode 0: y = A x;  1: y = r - A x;  2: y += A x;  3: y = x + (r - A x) / d (x != y)
 // Whether the solve-phase kernels would stream A as a long-row matrix (the
 // matrices that get a jagged copy).
@@ -328,7 +338,8 @@ bool csr_long_rows(const DCsr &A);
 void launch_jag_count(const DCsr &A, int32_t *cnt, hipStream_t s);
 void launch_jag_fill(const DCsr &A, Jag &J, int *bad, hipStream_t s);
 template <typename T>
-void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s);
+void launch_csr(int mode, const DCsr &A, const T *vals, const T *x, const T *r, const T *d, T *y, hipStream_t s,
+                KEvents ev = {});
 // y[map[i]] += eF[fmap[i]] (0 where fmap[i] < 0) + (A x)[i]: a level's prolongation
 // with its compact F correction, added into the finer level's vector through map
 template <typename T>
