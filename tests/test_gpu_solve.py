@@ -367,6 +367,30 @@ def test_kernel_timing_counts_and_bytes():
     assert 1.5 * nnz < per0 - b16 / n16 <= 2 * nnz, (per0, b16 / n16, nnz)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_kernel_timing_on_the_mid_size_stream_kernel(precision):
+    # config 3 (64^3): the coarse-grid matrix (262,144 rows) runs in the mid-size
+    # stream kernel, whose timed launches record their own events; the sweeps
+    # lie inside the V-cycles, so their summed time is below the V-cycles'
+    s = make_config(3)
+    g = gpu_solver(s, precision=precision)
+    g.set_kernel_timing(True)
+    x, info = g.solve(s.b, 1e-8)
+    assert info.status == 0
+    ms1, n1, _ = g.kernel_time(1)
+    ms2, n2, b2 = g.kernel_time(2)
+    ms0, n0, _ = g.kernel_time(0)
+    A3 = g.get_matrix(3, 0)
+    n3, nnz3 = A3[3][0], len(A3[1])
+    g.close()
+    assert n3 == 64 ** 3 and n1 == info.iterations and n2 == 3 * info.iterations
+    S = 8 if precision == "fp64" else 4
+    assert b2 / n2 == (S + 4) * nnz3 + 4 * (n3 + 1) + S * n3 + 3 * S * n3
+    assert 0 < ms2 < ms1 and ms0 > 0
+    print(f"[timing cfg3 {precision}] sweep {1e3 * ms2 / n2:.1f} us, V-cycle {1e3 * ms1 / n1:.1f} us, "
+          f"fine {1e3 * ms0 / n0:.1f} us", flush=True)
+
+
 def test_reused_device_blocks_give_the_same_bits():
     # a destroyed handle's device blocks are reused by the next handle (with the
     # old contents in them): the results must not depend on that
