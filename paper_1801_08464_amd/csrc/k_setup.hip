@@ -218,59 +218,29 @@ __global__ void k_level_maps(int64_t n, const int32_t *lab, int l, const int32_t
 
 // dinv_f = 1 / a_ii (i = flist[f]); err[3] = smallest level-local row with a zero diagonal.
 // offdiag |= 1 if some F row couples to another F point (A_FF not diagonal).
-__global__ void k_fdiag_inverse(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci,
-                                const double *v, double *dinv, int *err, int *offdiag, const int32_t *fmap) {
-    int64_t f = gtid();
-    if (f >= nF) return;
-    int64_t i = flist[f];
-    double d = 0.0;
+// (grid-stride over at most kReduceBlocks workgroups: the off-diagonal flag is
+// reduced per workgroup)
+__global__ void __launch_bounds__(kReduceBT) k_fdiag_inverse(int64_t nF, const int32_t *flist, const int32_t *rp,
+                                                             const int32_t *ci, const double *v, double *dinv,
+                                                             int *err, int *offdiag, const int32_t *fmap) {
+    __shared__ int sh[kReduceBT / kWave];
     bool off = false;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int64_t j = ci[p];
-        if (j == i) d = v[p];
-        else if (fmap[j] >= 0) off = true;
+    for (int64_t f = gtid(); f < nF; f += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = flist[f];
+        double d = 0.0;
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const int64_t j = ci[p];
+            if (j == i) d = v[p];
+            else if (fmap[j] >= 0) off = true;
+        }
+        if (d == 0.0) {
+            atomicMin(&err[3], (int)i);
+            dinv[f] = 0.0;
+        } else {
+            dinv[f] = 1.0 / d;
+        }
     }
-    if (off) atomicOr(offdiag, 1);
-    if (d == 0.0) {
-        atomicMin(&err[3], (int)i);
-        dinv[f] = 0.0;
-    } else {
-        dinv[f] = 1.0 / d;
-    }
-}
-
-// P = [W_p; I_C]: rows of the level, columns = C points
-__global__ void k_p_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cmap, int rp_type,
-                          int32_t *cnt) {
-    int64_t i = gtid();
-    if (i >= n) return;
-    int c = 0;
-    if (cmap[i] >= 0) c = 1;
-    else if (rp_type != 2)
-        for (int p = rp[i]; p < rp[i + 1]; ++p) c += cmap[ci[p]] >= 0;
-    cnt[i] = c;
-}
-
-__global__ void k_p_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *cmap,
-                         const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Prp, int32_t *Pci,
-                         double *Pv) {
-    int64_t i = gtid();
-    if (i >= n) return;
-    int q = Prp[i];
-    if (cmap[i] >= 0) {
-        Pci[q] = cmap[i];
-        Pv[q] = 1.0;
-        return;
-    }
-    if (rp_type == 2) return;
-    double di = dinv[fmap[i]];
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int j = ci[p];
-        if (cmap[j] < 0) continue;
-        Pci[q] = cmap[j];
-        Pv[q] = -(v[p] * di);
-        q++;
-    }
+    if (block_or_u32(off ? 1u : 0u, sh) && threadIdx.x == 0) atomicOr(offdiag, 1);
 }
 
 // R = [W_r, I_C]: rows = C points, columns = level-local indices
@@ -318,62 +288,6 @@ __global__ void k_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, co
 __global__ void k_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst) {
     int64_t i = gtid();
     if (i < n) dst[i] = src[idx[i]];
-}
-
-// A_FF: the F rows of A restricted to F columns, renumbered by fmap (order kept)
-__global__ void k_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci,
-                           const int32_t *fmap, int32_t *cnt) {
-    int64_t f = gtid();
-    if (f >= nF) return;
-    int64_t i = flist[f];
-    if (!fmap) {
-        cnt[f] = rp[i + 1] - rp[i];
-        return;
-    }
-    int c = 0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) c += fmap[ci[p]] >= 0;
-    cnt[f] = c;
-}
-
-__global__ void k_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
-                          const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv) {
-    int64_t f = gtid();
-    if (f >= nF) return;
-    int64_t i = flist[f];
-    int q = Frp[f];
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        const int j = fmap ? fmap[ci[p]] : ci[p];
-        if (j < 0) continue;
-        Fci[q] = j;
-        Fv[q] = v[p];
-        q++;
-    }
-}
-
-// The F columns of A (fmap >= 0) in every row, column numbers kept.  When the
-// error vector vanishes on the C points, the residual r - A e reads only these
-// entries; the skipped products are exact zeros, so the row sums are unchanged.
-__global__ void k_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt) {
-    int64_t i = gtid();
-    if (i >= n) return;
-    int c = 0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) c += fmap[ci[p]] >= 0;
-    cnt[i] = c;
-}
-
-__global__ void k_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
-                            const int32_t *Frp, int32_t *Fci, double *Fv, int fnum) {
-    int64_t i = gtid();
-    if (i >= n) return;
-    int q = Frp[i];
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        const int j = ci[p];
-        const int f = fmap[j];
-        if (f < 0) continue;
-        Fci[q] = fnum ? f : j;
-        Fv[q] = v[p];
-        q++;
-    }
 }
 
 // ---------------- SpGEMM: one wavefront per output row ----------------
@@ -856,6 +770,124 @@ struct InterpGroup {
     }
 };
 
+// ---------------- row selections: P = [W_p; I_C], A_FF, the F columns ----------------
+// A group of G lanes takes one row and its entries G at a time (coalesced
+// loads).  A kept entry's place is the row's start plus the number of kept
+// entries before it, counted by an ordered ballot over the group, so every
+// output row is in ascending column order, as a sequential loop writes it.
+// keep(p, col) decides entry p and sets its output column; emit(p, col, pos)
+// writes it.  Returns the row's count (the same in every lane of the group).
+template <int G, typename Keep, typename Emit>
+__device__ inline int group_select(const InterpGroup<G> &grp, int a, int b, int q, Keep keep, Emit emit) {
+    const unsigned long long below = (1ull << grp.lane) - 1ull;
+    for (int c0 = a; c0 < b; c0 += G) {
+        const int p = c0 + grp.lane;
+        int col = -1;
+        const bool k = p < b && keep(p, col);
+        const unsigned long long m = grp.ballot(k);
+        if (k) emit(p, col, q + __popcll(m & below));
+        q += __popcll(m);
+    }
+    return q;
+}
+
+// P = [W_p; I_C]: rows of the level, columns = C points.  FILL false: the row
+// counts into cnt; true: the entries at Prp.
+template <int G, bool FILL>
+__global__ void __launch_bounds__(256) k_p_sel(int64_t n, const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                               const int32_t *__restrict__ cmap, const int32_t *__restrict__ fmap,
+                                               const double *__restrict__ dinv, int rp_type,
+                                               const int32_t *__restrict__ Prp, int32_t *__restrict__ cnt,
+                                               int32_t *__restrict__ Pci, double *__restrict__ Pv) {
+    const InterpGroup<G> grp;
+    const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+    if (i >= n) return;  // uniform per group
+    const int ci_self = cmap[i];
+    if (ci_self >= 0 || rp_type == 2) {  // a C row (unit row), or W_p = 0
+        if (grp.lane == 0) {
+            if (!FILL) cnt[i] = ci_self >= 0 ? 1 : 0;
+            else if (ci_self >= 0) {
+                Pci[Prp[i]] = ci_self;
+                Pv[Prp[i]] = 1.0;
+            }
+        }
+        return;
+    }
+    auto keep = [&](int p, int &col) {
+        col = cmap[ci[p]];
+        return col >= 0;
+    };
+    if (FILL) {
+        const double di = dinv[fmap[i]];
+        group_select(grp, rp[i], rp[i + 1], Prp[i], keep, [&](int p, int col, int pos) {
+            Pci[pos] = col;
+            Pv[pos] = -(v[p] * di);
+        });
+    } else {
+        const int c = group_select(grp, rp[i], rp[i + 1], 0, keep, [](int, int, int) {});
+        if (grp.lane == 0) cnt[i] = c;
+    }
+}
+
+// A_FF: rows flist, the F columns renumbered by fmap (fmap null: every column,
+// unrenumbered: the compact copy of the F rows)
+template <int G, bool FILL>
+__global__ void __launch_bounds__(256) k_ff_sel(int64_t nF, const int32_t *__restrict__ flist,
+                                                const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                const double *__restrict__ v, const int32_t *__restrict__ fmap,
+                                                const int32_t *__restrict__ Frp, int32_t *__restrict__ cnt,
+                                                int32_t *__restrict__ Fci, double *__restrict__ Fv) {
+    const InterpGroup<G> grp;
+    const int64_t f = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+    if (f >= nF) return;  // uniform per group
+    const int64_t i = flist[f];
+    auto keep = [&](int p, int &col) {
+        const int j = ci[p];
+        col = fmap ? fmap[j] : j;
+        return col >= 0;
+    };
+    if (FILL) {
+        group_select(grp, rp[i], rp[i + 1], Frp[f], keep, [&](int p, int col, int pos) {
+            Fci[pos] = col;
+            Fv[pos] = v[p];
+        });
+    } else {
+        const int c = fmap ? group_select(grp, rp[i], rp[i + 1], 0, keep, [](int, int, int) {}) : rp[i + 1] - rp[i];
+        if (grp.lane == 0) cnt[f] = c;
+    }
+}
+
+// The F columns of A (fmap >= 0) in every row.  When the error vector vanishes
+// on the C points, the residual r - A e reads only these entries; the skipped
+// products are exact zeros, so the row sums are unchanged.  fnum: the columns as
+// F indices (fmap[j]) instead of level rows.
+template <int G, bool FILL>
+__global__ void __launch_bounds__(256) k_fcol_sel(int64_t n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                  const int32_t *__restrict__ fmap, const int32_t *__restrict__ Frp,
+                                                  int32_t *__restrict__ cnt, int32_t *__restrict__ Fci,
+                                                  double *__restrict__ Fv, int fnum) {
+    const InterpGroup<G> grp;
+    const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+    if (i >= n) return;  // uniform per group
+    auto keep = [&](int p, int &col) {
+        const int j = ci[p];
+        const int f = fmap[j];
+        col = fnum ? f : j;
+        return f >= 0;
+    };
+    if (FILL) {
+        group_select(grp, rp[i], rp[i + 1], Frp[i], keep, [&](int p, int col, int pos) {
+            Fci[pos] = col;
+            Fv[pos] = v[p];
+        });
+    } else {
+        const int c = group_select(grp, rp[i], rp[i + 1], 0, keep, [](int, int, int) {});
+        if (grp.lane == 0) cnt[i] = c;
+    }
+}
+
 template <int G, int MAXC, int LO>
 __global__ void __launch_bounds__(256) k_interp_fill_grp(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ v,
@@ -1098,17 +1130,37 @@ void launch_level_maps(int64_t n, const int32_t *lab, int l, const int32_t *fpos
 }
 void launch_fdiag_inverse(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
                           double *dinv, int *err, int *offdiag_flag, const int32_t *fmap, hipStream_t s) {
-    if (nF > 0)
-        k_fdiag_inverse<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, v, dinv, err, offdiag_flag, fmap);
+    if (nF > 0) {
+        const unsigned g = nblocks(nF, kReduceBT);
+        k_fdiag_inverse<<<g < kReduceBlocks ? g : kReduceBlocks, kReduceBT, 0, s>>>(nF, flist, rp, ci, v, dinv, err,
+                                                                                    offdiag_flag, fmap);
+    }
 }
-void launch_p_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cmap, int rp_type, int32_t *cnt,
-                    hipStream_t s) {
-    if (n > 0) k_p_count<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, cmap, rp_type, cnt);
+// lanes per row of the row selections, from the mean row length of the matrix
+int select_lanes(int64_t nrows, int64_t nnz) {
+    const double avg = nrows > 0 ? (double)nnz / (double)nrows : 0.0;
+    return avg < 6.0 ? 4 : avg < 12.0 ? 8 : avg < 24.0 ? 16 : 32;
 }
-void launch_p_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *cmap,
+#define MGR_SEL(KERNEL, FILL, LANES, N, ...)                                                        \
+    do {                                                                                           \
+        switch (LANES) {                                                                           \
+        case 4: KERNEL<4, FILL><<<nblocks(N, 256 / 4), 256, 0, s>>>(__VA_ARGS__); break;          \
+        case 8: KERNEL<8, FILL><<<nblocks(N, 256 / 8), 256, 0, s>>>(__VA_ARGS__); break;          \
+        case 16: KERNEL<16, FILL><<<nblocks(N, 256 / 16), 256, 0, s>>>(__VA_ARGS__); break;       \
+        default: KERNEL<32, FILL><<<nblocks(N, 256 / 32), 256, 0, s>>>(__VA_ARGS__); break;       \
+        }                                                                                          \
+    } while (0)
+void launch_p_count(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cmap, int rp_type,
+                    int32_t *cnt, hipStream_t s) {
+    if (n > 0)
+        MGR_SEL(k_p_sel, false, lanes, n, n, rp, ci, nullptr, cmap, nullptr, nullptr, rp_type, nullptr, cnt, nullptr,
+                nullptr);
+}
+void launch_p_fill(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *cmap,
                    const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Prp, int32_t *Pci, double *Pv,
                    hipStream_t s) {
-    if (n > 0) k_p_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, cmap, fmap, dinv, rp_type, Prp, Pci, Pv);
+    if (n > 0)
+        MGR_SEL(k_p_sel, true, lanes, n, n, rp, ci, v, cmap, fmap, dinv, rp_type, Prp, nullptr, Pci, Pv);
 }
 void launch_r_count(int64_t nC, const int32_t *clist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
                     int rp_type, int32_t *cnt, hipStream_t s) {
@@ -1123,22 +1175,23 @@ void launch_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, const in
 void launch_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst, hipStream_t s) {
     if (n > 0) k_gather_i32<<<nblocks(n, BT), BT, 0, s>>>(n, idx, src, dst);
 }
-void launch_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
-                     int32_t *cnt, hipStream_t s) {
-    if (nF > 0) k_ff_count<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, fmap, cnt);
+void launch_ff_count(int lanes, int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci,
+                     const int32_t *fmap, int32_t *cnt, hipStream_t s) {
+    if (nF > 0) MGR_SEL(k_ff_sel, false, lanes, nF, nF, flist, rp, ci, nullptr, fmap, nullptr, cnt, nullptr, nullptr);
 }
-void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
+void launch_ff_fill(int lanes, int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
                     const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s) {
-    if (nF > 0) k_ff_fill<<<nblocks(nF, BT), BT, 0, s>>>(nF, flist, rp, ci, v, fmap, Frp, Fci, Fv);
+    if (nF > 0) MGR_SEL(k_ff_sel, true, lanes, nF, nF, flist, rp, ci, v, fmap, Frp, nullptr, Fci, Fv);
 }
-void launch_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt,
+void launch_fcol_count(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt,
                        hipStream_t s) {
-    if (n > 0) k_fcol_count<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, fmap, cnt);
+    if (n > 0) MGR_SEL(k_fcol_sel, false, lanes, n, n, rp, ci, nullptr, fmap, nullptr, cnt, nullptr, nullptr, 0);
 }
-void launch_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
+void launch_fcol_fill(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
                       const int32_t *Frp, int32_t *Fci, double *Fv, bool fnum, hipStream_t s) {
-    if (n > 0) k_fcol_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, fmap, Frp, Fci, Fv, fnum ? 1 : 0);
+    if (n > 0) MGR_SEL(k_fcol_sel, true, lanes, n, n, rp, ci, v, fmap, Frp, nullptr, Fci, Fv, fnum ? 1 : 0);
 }
+#undef MGR_SEL
 int spgemm_max_row() { return kWave * kSpgChunks; }
 void launch_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx, hipStream_t s) {
     if (m <= 0) return;

@@ -390,6 +390,7 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     MgrLevel &lv = h->lev[l];
     const DCsr &A = lv.A;
     const int64_t n = A.nrows;
+    const int sel = select_lanes(A.nrows, A.nnz);  // lanes per row of the row selections
     lv.n = n;
     ScratchScope scope(h);
     Tmp<int32_t> isF(h, n), isC(h, n), fpos(h, n + 1), cpos(h, n + 1);
@@ -409,14 +410,14 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     // in-place F-relaxation, at the levels whose cycle uses them
     if (lv.nF > 0 && ((l == 0 && h->o.global_relax) || h->o.f_sweeps > 1 || h->o.cycle_post)) {
         Tmp<int32_t> cnt(h, lv.nF);
-        launch_ff_count(lv.nF, lv.flist, A.rp, A.ci, nullptr, cnt.p, h->stream);
+        launch_ff_count(sel, lv.nF, lv.flist, A.rp, A.ci, nullptr, cnt.p, h->stream);
         lv.AF.nrows = lv.nF;
         lv.AF.ncols = n;
         lv.AF.rp = dalloc<int32_t>(h, lv.nF + 1);
         lv.AF.nnz = scan(h, cnt.p, lv.AF.rp, lv.nF);
         lv.AF.ci = dalloc<int32_t>(h, lv.AF.nnz);
         lv.AF.v = dalloc<double>(h, lv.AF.nnz);
-        launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
+        launch_ff_fill(sel, lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
         lv.flanes = choose_lanes(lv.AF);
     }
     // the F columns of A (all rows) for the residual that precedes the
@@ -426,26 +427,26 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     if (lv.nF > 0 && !h->o.cycle_post && !(l == 0 && h->o.global_relax)) {
         lv.fcompact = h->o.f_sweeps == 1;
         Tmp<int32_t> cnt(h, n);
-        launch_fcol_count(n, A.rp, A.ci, lv.fmap, cnt.p, h->stream);
+        launch_fcol_count(sel, n, A.rp, A.ci, lv.fmap, cnt.p, h->stream);
         lv.AcF.nrows = n;
         lv.AcF.ncols = lv.fcompact ? lv.nF : n;
         lv.AcF.rp = dalloc<int32_t>(h, n + 1);
         lv.AcF.nnz = scan(h, cnt.p, lv.AcF.rp, n);
         lv.AcF.ci = dalloc<int32_t>(h, lv.AcF.nnz);
         lv.AcF.v = dalloc<double>(h, lv.AcF.nnz);
-        launch_fcol_fill(n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, lv.fcompact, h->stream);
+        launch_fcol_fill(sel, n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, lv.fcompact, h->stream);
     }
     // optional F-relaxation by one AMG V-cycle on A_FF
     if (((h->o.frelax_amg_mask >> l) & 1) && lv.nF > 0) {
         Tmp<int32_t> cnt(h, lv.nF);
         DCsr Aff;
         Aff.nrows = Aff.ncols = lv.nF;
-        launch_ff_count(lv.nF, lv.flist, A.rp, A.ci, lv.fmap, cnt.p, h->stream);
+        launch_ff_count(sel, lv.nF, lv.flist, A.rp, A.ci, lv.fmap, cnt.p, h->stream);
         Aff.rp = dalloc<int32_t>(h, lv.nF + 1);
         Aff.nnz = scan(h, cnt.p, Aff.rp, lv.nF);
         Aff.ci = dalloc<int32_t>(h, Aff.nnz);
         Aff.v = dalloc<double>(h, Aff.nnz);
-        launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, Aff.rp, Aff.ci, Aff.v, h->stream);
+        launch_ff_fill(sel, lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, Aff.rp, Aff.ci, Aff.v, h->stream);
         lv.Aff = Aff;
         lv.ff = std::make_shared<AmgHier>();
         AmgArenaScope amg_arena(h);
@@ -455,14 +456,14 @@ void build_mgr_level(mgr_handle *h, int l, DCsr &Anext, int32_t *&lab_next, int3
     // P = [W_p; I]
     {
         Tmp<int32_t> cnt(h, n);
-        launch_p_count(n, A.rp, A.ci, lv.cmap, rp_type, cnt.p, h->stream);
+        launch_p_count(sel, n, A.rp, A.ci, lv.cmap, rp_type, cnt.p, h->stream);
         lv.P.nrows = n;
         lv.P.ncols = lv.nC;
         lv.P.rp = dalloc<int32_t>(h, n + 1);
         lv.P.nnz = scan(h, cnt.p, lv.P.rp, n);
         lv.P.ci = dalloc<int32_t>(h, lv.P.nnz);
         lv.P.v = dalloc<double>(h, lv.P.nnz);
-        launch_p_fill(n, A.rp, A.ci, A.v, lv.cmap, lv.fmap, lv.dinv, rp_type, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
+        launch_p_fill(sel, n, A.rp, A.ci, A.v, lv.cmap, lv.fmap, lv.dinv, rp_type, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
     }
     // R = [W_r, I]
     {
@@ -1511,19 +1512,20 @@ int check_options(const mgr_options *o, std::string &why) {
 void update_mgr_level(mgr_handle *h, int l, DCsr &Anext) {
     MgrLevel &lv = h->lev[l];
     const DCsr &A = lv.A;
+    const int sel = select_lanes(A.nrows, A.nnz);
     ScratchScope scope(h);
     fdiag_inverse(h, l);
-    if (lv.AF.v) launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
+    if (lv.AF.v) launch_ff_fill(sel, lv.nF, lv.flist, A.rp, A.ci, A.v, nullptr, lv.AF.rp, lv.AF.ci, lv.AF.v, h->stream);
     if (lv.AcF.v)
-        launch_fcol_fill(lv.n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, lv.fcompact, h->stream);
+        launch_fcol_fill(sel, lv.n, A.rp, A.ci, A.v, lv.fmap, lv.AcF.rp, lv.AcF.ci, lv.AcF.v, lv.fcompact, h->stream);
     if (lv.Aff.v) {  // the level relaxes its F points with an AMG cycle on A_FF
-        launch_ff_fill(lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, lv.Aff.rp, lv.Aff.ci, lv.Aff.v, h->stream);
+        launch_ff_fill(sel, lv.nF, lv.flist, A.rp, A.ci, A.v, lv.fmap, lv.Aff.rp, lv.Aff.ci, lv.Aff.v, h->stream);
         lv.ff = std::make_shared<AmgHier>();
         AmgArenaScope amg_arena(h);
         build_amg(h, *lv.ff, lv.Aff, h->o.frelax_amg_pre, h->o.frelax_amg_post);
     }
     const int rp_type = h->o.rp_type;
-    launch_p_fill(lv.n, A.rp, A.ci, A.v, lv.cmap, lv.fmap, lv.dinv, rp_type, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
+    launch_p_fill(sel, lv.n, A.rp, A.ci, A.v, lv.cmap, lv.fmap, lv.dinv, rp_type, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
     launch_r_fill(lv.nC, lv.clist, A.rp, A.ci, A.v, lv.fmap, lv.dinv, rp_type, lv.R.rp, lv.R.ci, lv.R.v,
                   h->stream);
     DCsr T = spgemm(h, A, lv.P, true);

@@ -263,9 +263,13 @@ void launch_level_maps(int64_t n, const int32_t *lab, int l, const int32_t *fpos
                        int32_t *cmap, int32_t *flist, int32_t *clist, hipStream_t s);
 void launch_fdiag_inverse(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
                           double *dinv, int *err, int *offdiag_flag, const int32_t *fmap, hipStream_t s);
-void launch_p_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cmap, int rp_type, int32_t *cnt,
-                    hipStream_t s);
-void launch_p_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *cmap,
+// The row selections below take `lanes` lanes per row (4, 8, 16 or 32; from
+// select_lanes, by the matrix's mean row length); every output row keeps the
+// source row's column order.
+int select_lanes(int64_t nrows, int64_t nnz);
+void launch_p_count(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *cmap, int rp_type,
+                    int32_t *cnt, hipStream_t s);
+void launch_p_fill(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *cmap,
                    const int32_t *fmap, const double *dinv, int rp_type, const int32_t *Prp, int32_t *Pci, double *Pv,
                    hipStream_t s);
 void launch_r_count(int64_t nC, const int32_t *clist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
@@ -276,14 +280,14 @@ void launch_r_fill(int64_t nC, const int32_t *clist, const int32_t *rp, const in
 void launch_gather_i32(int64_t n, const int32_t *idx, const int32_t *src, int32_t *dst, hipStream_t s);
 // A_FF: rows flist, columns with fmap >= 0 renumbered by fmap (fmap null: every
 // column kept unrenumbered, the compact copy of the F rows)
-void launch_ff_count(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const int32_t *fmap,
-                     int32_t *cnt, hipStream_t s);
-void launch_ff_fill(int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
+void launch_ff_count(int lanes, int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci,
+                     const int32_t *fmap, int32_t *cnt, hipStream_t s);
+void launch_ff_fill(int lanes, int64_t nF, const int32_t *flist, const int32_t *rp, const int32_t *ci, const double *v,
                     const int32_t *fmap, const int32_t *Frp, int32_t *Fci, double *Fv, hipStream_t s);
-void launch_fcol_count(int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt,
+void launch_fcol_count(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const int32_t *fmap, int32_t *cnt,
                        hipStream_t s);
 // the F columns of every row; fnum: columns as F indices (fmap[j]) instead of level rows
-void launch_fcol_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
+void launch_fcol_fill(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
                       const int32_t *Frp, int32_t *Fci, double *Fv, bool fnum, hipStream_t s);
 // SpGEMM C = A B, canonical ascending-k summation.  pass 0 counts into cnt, pass 1 fills.
 // group = lanes per output row (8, 16, 32, 64); rows of A may hold up to group * 8 entries.
