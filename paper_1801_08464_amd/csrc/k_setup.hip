@@ -733,8 +733,8 @@ __global__ void k_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, c
 // walk the group's ballot masks in ascending lane order, chunk after chunk, so
 // every sum runs in the order above whatever G is.  G = 16 serves the rows with
 // at most 32 strong C neighbours (most rows: a wavefront per row would leave
-// most lanes idle), G = 64 those with up to kInterpMaxC; longer rows are left
-// to k_interp_fill.
+// most lanes idle; G = 8 where the matrix's rows are short), G = 64 those with
+// up to kInterpMaxC; longer rows are left to k_interp_fill.
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1269,12 +1269,23 @@ void launch_interp_count(int64_t n, const int32_t *rp, const int32_t *ci, const 
                          int32_t *cnt, hipStream_t s) {
     if (n > 0) k_interp_count<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, sflag, cf, cnt);
 }
-void launch_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *sflag,
-                        const int32_t *cf, const int32_t *cmap, const int32_t *Prp, int32_t *Pci, double *Pv,
-                        hipStream_t s) {
+void launch_interp_fill(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
+                        const uint8_t *sflag, const int32_t *cf, const int32_t *cmap, const int32_t *Prp, int32_t *Pci,
+                        double *Pv, hipStream_t s) {
     if (n <= 0) return;
-    k_interp_fill_grp<16, kInterpSmallC, 0><<<nblocks(n, 256 / 16), 256, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp,
-                                                                                 Pci, Pv);
+    // the group follows the mean row length: 8 lanes below 12 entries (the F
+    // blocks of the MGR levels), 16 below 28 (the coarse grid: 32 lanes took
+    // 3.3 against 3.1 ms there), 32 above (its first AMG levels: 1.74 against
+    // 1.94 ms on the first)
+    if (nnz < 12 * n)
+        k_interp_fill_grp<8, kInterpSmallC, 0><<<nblocks(n, 256 / 8), 256, 0, s>>>(n, rp, ci, v, sflag, cf, cmap,
+                                                                                   Prp, Pci, Pv);
+    else if (nnz < 28 * n)
+        k_interp_fill_grp<16, kInterpSmallC, 0><<<nblocks(n, 256 / 16), 256, 0, s>>>(n, rp, ci, v, sflag, cf, cmap,
+                                                                                     Prp, Pci, Pv);
+    else
+        k_interp_fill_grp<32, kInterpSmallC, 0><<<nblocks(n, 256 / 32), 256, 0, s>>>(n, rp, ci, v, sflag, cf, cmap,
+                                                                                     Prp, Pci, Pv);
     k_interp_fill_grp<kWave, kInterpMaxC, kInterpSmallC><<<nblocks(n, 256 / kWave), 256, 0, s>>>(
         n, rp, ci, v, sflag, cf, cmap, Prp, Pci, Pv);
     k_interp_fill<<<nblocks(n, BT), BT, 0, s>>>(n, rp, ci, v, sflag, cf, cmap, Prp, Pci, Pv);

@@ -690,7 +690,8 @@ void build_amg(mgr_handle *h, AmgHier &H, const DCsr &Atop, int pre, int post) {
                 lv.P.nnz = scan(h, cnt.p, lv.P.rp, n);
                 lv.P.ci = dalloc<int32_t>(h, lv.P.nnz);
                 lv.P.v = dalloc<double>(h, lv.P.nnz);
-                launch_interp_fill(n, A.rp, A.ci, A.v, sflag.p, lv.cf, cmap.p, lv.P.rp, lv.P.ci, lv.P.v, h->stream);
+                launch_interp_fill(n, A.nnz, A.rp, A.ci, A.v, sflag.p, lv.cf, cmap.p, lv.P.rp, lv.P.ci, lv.P.v,
+                                   h->stream);
                 lv.PT = transpose(h, lv.P, true);
                 DCsr T = spgemm(h, A, lv.P, true);
                 DCsr Ac = spgemm(h, lv.PT, T);

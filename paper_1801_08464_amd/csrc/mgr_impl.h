@@ -312,9 +312,9 @@ void launch_pmis_update(int64_t n, const int32_t *Srp, const int32_t *Sci, const
 void launch_cf_flags(int64_t n, const int32_t *state, int32_t *isC, hipStream_t s);
 void launch_interp_count(int64_t n, const int32_t *rp, const int32_t *ci, const uint8_t *sflag, const int32_t *cf,
                          int32_t *cnt, hipStream_t s);
-void launch_interp_fill(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const uint8_t *sflag,
-                        const int32_t *cf, const int32_t *cmap, const int32_t *Prp, int32_t *Pci, double *Pv,
-                        hipStream_t s);
+void launch_interp_fill(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *v,
+                        const uint8_t *sflag, const int32_t *cf, const int32_t *cmap, const int32_t *Prp, int32_t *Pci,
+                        double *Pv, hipStream_t s);
 void launch_l1(int64_t n, const int32_t *rp, const double *v, double *l1, int *err, hipStream_t s);
 void launch_dense_lu(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double *lu, int32_t *perm,
                      int *err, hipStream_t s);
