@@ -310,8 +310,11 @@ __device__ inline int group_min_i32(int v) {
 // G lanes (an aligned group of the wavefront) per output row.  Each lane keeps,
 // per chunk, the head column and (fill pass) the head value of its B row, loaded
 // together so a merge step waits on one load.  Output t of the row is held by
-// lane t mod G and the group writes G outputs at a time (coalesced).
-template <bool FILL, int G>
+// lane t mod G and the group writes G outputs at a time (coalesced).  NCH chunks
+// per lane (rows of up to G * NCH entries): the fill pass takes the fewest that
+// hold the operand's longest row, since its registers per chunk set how many
+// wavefronts a SIMD holds, and the merge waits on loads.
+template <bool FILL, int G, int NCH>
 __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__restrict__ Arp,
                                                 const int32_t *__restrict__ Aci, const double *__restrict__ Av,
                                                 const int32_t *__restrict__ Brp, const int32_t *__restrict__ Bci,
@@ -323,7 +326,7 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
     if (row >= m) return;  // uniform per group
     const int a0 = Arp[row];
     const int len = Arp[row + 1] - a0;
-    if (len > G * kSpgChunks) {  // too long for this group size: flagged, counted as empty
+    if (len > G * NCH) {  // too long for this group size: flagged, counted as empty
         if (glane == 0) {
             atomicOr(err, 1);
             if (!FILL) cnt_or_Crp[row] = 0;
@@ -332,10 +335,10 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
     }
     const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
     const int nch = (len + G - 1) / G;
-    int p[kSpgChunks], e[kSpgChunks], hd[kSpgChunks];
-    double av[kSpgChunks], hv[kSpgChunks];
+    int p[NCH], e[NCH], hd[NCH];
+    double av[NCH], hv[NCH];
 #pragma unroll
-    for (int c = 0; c < kSpgChunks; ++c) {
+    for (int c = 0; c < NCH; ++c) {
         p[c] = 0;
         e[c] = 0;
         hd[c] = INT_MAX;
@@ -360,14 +363,14 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
     for (;;) {
         int mn = INT_MAX;
 #pragma unroll
-        for (int c = 0; c < kSpgChunks; ++c)
+        for (int c = 0; c < NCH; ++c)
             if (c < nch) mn = hd[c] < mn ? hd[c] : mn;
         mn = group_min_i32<G>(mn);
         if (mn == INT_MAX) break;
         if (FILL) {
             double acc = 0.0;
 #pragma unroll
-            for (int c = 0; c < kSpgChunks; ++c) {
+            for (int c = 0; c < NCH; ++c) {
                 if (c < nch) {
                     bool hit = hd[c] == mn;
                     double prod = hit ? av[c] * hv[c] : 0.0;
@@ -391,7 +394,7 @@ __global__ void __launch_bounds__(256) k_spgemm(int64_t m, const int32_t *__rest
         }
         count++;
 #pragma unroll
-        for (int c = 0; c < kSpgChunks; ++c) {
+        for (int c = 0; c < NCH; ++c) {
             if (c < nch && hd[c] == mn) {
                 p[c]++;
                 if (p[c] < e[c]) {
@@ -1199,20 +1202,31 @@ void launch_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int
     const unsigned g = g0 < (unsigned)kLenStatBlocks ? g0 : (unsigned)kLenStatBlocks;
     k_row_len_stats<<<g, kLenStatBT, 0, s>>>(m, list, rp, sum, mx);
 }
-template <bool FILL, int G>
+template <bool FILL, int G, int NCH>
 static void spgemm_g(int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av, const int32_t *Brp,
                      const int32_t *Bci, const double *Bv, int32_t *c, int32_t *Cci, double *Cv, int *err,
                      hipStream_t s) {
-    k_spgemm<FILL, G><<<nblocks(m, BT / G), BT, 0, s>>>(m, Arp, Aci, Av, Brp, Bci, Bv, c, Cci, Cv, err);
+    k_spgemm<FILL, G, NCH><<<nblocks(m, BT / G), BT, 0, s>>>(m, Arp, Aci, Av, Brp, Bci, Bv, c, Cci, Cv, err);
 }
-void launch_spgemm(int pass, int group, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av,
+template <int G>
+static void spgemm_fill_g(int nch, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av,
+                          const int32_t *Brp, const int32_t *Bci, const double *Bv, int32_t *c, int32_t *Cci,
+                          double *Cv, int *err, hipStream_t s) {
+    switch (nch) {
+    case 1: spgemm_g<true, G, 1>(m, Arp, Aci, Av, Brp, Bci, Bv, c, Cci, Cv, err, s); break;
+    case 2: spgemm_g<true, G, 2>(m, Arp, Aci, Av, Brp, Bci, Bv, c, Cci, Cv, err, s); break;
+    case 4: spgemm_g<true, G, 4>(m, Arp, Aci, Av, Brp, Bci, Bv, c, Cci, Cv, err, s); break;
+    default: spgemm_g<true, G, kSpgChunks>(m, Arp, Aci, Av, Brp, Bci, Bv, c, Cci, Cv, err, s); break;
+    }
+}
+void launch_spgemm(int pass, int group, int nch, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av,
                    const int32_t *Brp, const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci,
                    double *Cv, int *err, hipStream_t s) {
     if (m <= 0) return;
-#define MGR_SPG(G)                                                                                     \
-    do {                                                                                               \
-        if (pass == 0) spgemm_g<false, G>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err, s); \
-        else spgemm_g<true, G>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err, s);            \
+#define MGR_SPG(G)                                                                                                \
+    do {                                                                                                          \
+        if (pass == 0) spgemm_g<false, G, kSpgChunks>(m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err, s); \
+        else spgemm_fill_g<G>(nch, m, Arp, Aci, Av, Brp, Bci, Bv, cnt_or_Crp, Cci, Cv, err, s);                    \
     } while (0)
     switch (group) {
     case 4: MGR_SPG(4); break;

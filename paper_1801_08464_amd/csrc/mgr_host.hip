@@ -255,6 +255,22 @@ int spgemm_group(int maxlen) {
     return maxlen <= 32 ? 4 : maxlen <= 64 ? 8 : maxlen <= 128 ? 16 : maxlen <= 256 ? 32 : 64;
 }
 
+// chunks per lane of the fill pass: the fewest (1, 2, 4, 8) whose group * nch
+// entries hold A's longest row
+int spgemm_chunks(int group, int maxlen) {
+    const int need = (maxlen + group - 1) / group;
+    return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+}
+
+// the fill pass's group: at least the count's, and wide enough that four
+// chunks per lane hold the longest row (eight chunks take twice the registers
+// and halve the wavefronts a SIMD holds; the row counts do not depend on the
+// group)
+int spgemm_fill_group(int group, int maxlen) {
+    while (group < kWave && group * 4 < maxlen) group *= 2;
+    return group;
+}
+
 DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     DCsr C;
     C.nrows = A.nrows;
@@ -266,27 +282,28 @@ DCsr spgemm(mgr_handle *h, const DCsr &A, const DCsr &B, bool scratch = false) {
     // to the group that the longest row needs
     int group = spgemm_group(A.nrows > 0 ? (int)(2 * A.nnz / A.nrows + 1) : 0);
     reset_err(h);
-    launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
+    // A's longest row (into the error word 1, read back with the scan total)
+    launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
+    launch_spgemm(0, group, 8, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
                   h->stream);
     C.nnz = scan(h, cnt.p, C.rp, A.nrows, true);
+    const int maxlen = h->herr[1];
     if (h->herr[6]) {
-        reset_err(h);
-        launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
-        read_err(h);
-        const int maxlen = h->herr[1];
         if (maxlen > spgemm_max_row())
             throw_err(h, MGR_E_INVALID,
                       "SpGEMM: a left-operand row exceeds " + std::to_string(spgemm_max_row()) + " entries");
         group = spgemm_group(maxlen);
         reset_err(h);
-        launch_spgemm(0, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
+        launch_spgemm(0, group, 8, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, cnt.p, nullptr, nullptr, h->derr + 6,
                       h->stream);
         C.nnz = scan(h, cnt.p, C.rp, A.nrows, true);
         if (h->herr[6]) throw_err(h, MGR_E_INVALID, "SpGEMM: row length check failed");
     }
     C.ci = scratch ? salloc<int32_t>(h, C.nnz) : dalloc<int32_t>(h, C.nnz);
     C.v = scratch ? salloc<double>(h, C.nnz) : dalloc<double>(h, C.nnz);
-    launch_spgemm(1, group, A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v, h->derr + 6, h->stream);
+    const int fgroup = spgemm_fill_group(group, maxlen);
+    launch_spgemm(1, fgroup, spgemm_chunks(fgroup, maxlen), A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci,
+                  C.v, h->derr + 6, h->stream);
     return C;
 }
 
@@ -313,8 +330,10 @@ void spgemm_values(mgr_handle *h, const DCsr &A, const DCsr &B, DCsr &C) {
     reset_err(h);
     launch_row_len_stats(A.nrows, nullptr, A.rp, nullptr, h->derr + 1, h->stream);
     read_err(h);
+    // (read before reset_err clears the host copy of the error words)
+    const int maxlen = h->herr[1], group = spgemm_fill_group(spgemm_group(maxlen), maxlen);
     reset_err(h);
-    launch_spgemm(1, spgemm_group(h->herr[1]), A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v,
+    launch_spgemm(1, group, spgemm_chunks(group, maxlen), A.nrows, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v,
                   h->derr + 6, h->stream);
     read_err(h);
     if (h->herr[6]) throw_err(h, MGR_E_INVALID, "SpGEMM: row length check failed");

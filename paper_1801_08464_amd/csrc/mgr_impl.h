@@ -290,10 +290,12 @@ void launch_fcol_count(int lanes, int64_t n, const int32_t *rp, const int32_t *c
 void launch_fcol_fill(int lanes, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, const int32_t *fmap,
                       const int32_t *Frp, int32_t *Fci, double *Fv, bool fnum, hipStream_t s);
 // SpGEMM C = A B, canonical ascending-k summation.  pass 0 counts into cnt, pass 1 fills.
-// group = lanes per output row (8, 16, 32, 64); rows of A may hold up to group * 8 entries.
+// group = lanes per output row (4, 8, 16, 32, 64); rows of A may hold up to group * 8
+// entries.  nch (fill pass): chunks per lane, 1, 2, 4 or 8, with group * nch at
+// least A's longest row.
 int spgemm_max_row();
 void launch_row_len_stats(int64_t m, const int32_t *list, const int32_t *rp, int *sum, int *mx, hipStream_t s);
-void launch_spgemm(int pass, int group, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av,
+void launch_spgemm(int pass, int group, int nch, int64_t m, const int32_t *Arp, const int32_t *Aci, const double *Av,
                    const int32_t *Brp, const int32_t *Bci, const double *Bv, int32_t *cnt_or_Crp, int32_t *Cci,
                    double *Cv, int *err, hipStream_t s);
 // stable transpose: count (atomics), fill (atomics), then per-row sort by source row
