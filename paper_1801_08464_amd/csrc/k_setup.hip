@@ -746,6 +746,9 @@ __device__ inline void wave_sync() {
 }
 
 constexpr int kInterpSmallC = 32;  // strong C neighbours per row of the 16-lane form
+// chunks of G entries of a strong F neighbour's row held in registers (longer
+// rows take three passes over memory instead)
+constexpr int kInterpRowChunks = 4;
 
 template <int G>
 struct InterpGroup {
@@ -960,6 +963,48 @@ __global__ void __launch_bounds__(256) k_interp_fill_grp(
             const int k = grp.shfl(j, l);
             const double aik = grp.shfl(vv, l);
             const int ka = rp[k], kb = rp[k + 1];
+            if (kb - ka <= G * kInterpRowChunks) {
+                // row k in registers: its columns and values loaded once (all
+                // chunks together), its C positions found once; the same sums
+                // in the same order as the passes below
+                int qc[kInterpRowChunks], qp[kInterpRowChunks];
+                double qv[kInterpRowChunks];
+#pragma unroll
+                for (int u = 0; u < kInterpRowChunks; ++u) {
+                    const int q = ka + u * G + lane;
+                    qc[u] = q < kb ? ci[q] : -1;
+                    qv[u] = q < kb ? v[q] : 0.0;
+                }
+                double akk = 0.0;
+#pragma unroll
+                for (int u = 0; u < kInterpRowChunks; ++u) {
+                    const unsigned long long md = grp.ballot(qc[u] == k);
+                    if (md) akk = grp.shfl(qv[u], __builtin_ctzll(md));
+                }
+#pragma unroll
+                for (int u = 0; u < kInterpRowChunks; ++u)
+                    qp[u] = (qc[u] >= 0 && cf[qc[u]] == 1) ? find_col(cols, nc, cmap[qc[u]]) : -1;
+                double den = 0.0;
+#pragma unroll
+                for (int u = 0; u < kInterpRowChunks; ++u) {
+                    const double abar = (qv[u] * akk < 0.0) ? qv[u] : 0.0;
+                    den = grp.ordered_add(den, grp.ballot(qp[u] >= 0), abar);
+                }
+                if (den == 0.0) {
+                    atil = atil + aik;
+                    continue;
+                }
+#pragma unroll
+                for (int u = 0; u < kInterpRowChunks; ++u) {
+                    if (qp[u] >= 0) {
+                        const double abar = (qv[u] * akk < 0.0) ? qv[u] : 0.0;
+                        const double prod = aik * abar;
+                        num[qp[u]] = num[qp[u]] + prod / den;
+                    }
+                }
+                wave_sync();
+                continue;
+            }
             double akk = 0.0;
             for (int d0 = ka; d0 < kb; d0 += G) {
                 const int q = d0 + lane;
