@@ -190,6 +190,28 @@ def test_update_values_is_bitwise_a_new_setup(orc):
         g.close()
 
 
+def test_update_values_long_rows():
+    # the value-only Galerkin products size their lane groups from the longest
+    # left-operand row they read back; on the long-row system (AMG rows of more
+    # than 256 entries) the update must still equal a fresh setup bit for bit
+    s = long_row_system()
+    s2 = _perturbed(s, 13)
+    g = gpu_solver(s, frelax_amg_mask=2)
+    f = gpu_solver(s2, frelax_amg_mask=2)
+    try:
+        g.update_values(s2.data)
+        xa, ia = g.solve(s2.b, 1e-9)
+        xb, ib = f.solve(s2.b, 1e-9)
+        assert ia.status == ib.status == 0 and ia.iterations == ib.iterations
+        np.testing.assert_array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+        for kind, lvl in [(0, 1), (0, 2)] + [(3, k) for k in range(g.levels[1])]:
+            for x, y in zip(g.get_matrix(kind, lvl)[:3], f.get_matrix(kind, lvl)[:3]):
+                np.testing.assert_array_equal(x, y)
+    finally:
+        g.close()
+        f.close()
+
+
 @pytest.mark.parametrize("opts", [dict(precision="mixed"), dict(transpose=True), dict(frelax_amg_mask=6)])
 def test_update_values_forms(opts):
     s = small_system((17, 15, 5), seed=6, sigma=1.5, frac=0.35, region="ball")
