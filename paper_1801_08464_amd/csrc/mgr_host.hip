@@ -907,9 +907,10 @@ double csr_bytes(const DCsr &A, int mode, double S) {
 // timing is on
 template <typename T>
 void fine_op(mgr_handle *h, int mode, const T *x, const T *r, T *y) {
-    launch_csell<T>(mode, h->A0s, P_<T>::v(h->A0s), x, r, y, h->stream,
-                    h->timing ? timer_kernel(h, h->tm[0]) : KEvents{});
-    if (h->timing) {
+    // (events only for a launch that happens: an empty operator launches nothing)
+    const bool timed = h->timing && h->A0s.nslice > 0;
+    launch_csell<T>(mode, h->A0s, P_<T>::v(h->A0s), x, r, y, h->stream, timed ? timer_kernel(h, h->tm[0]) : KEvents{});
+    if (timed) {
         // values + columns of the true nonzeros, row pointers, x and y, plus r
         // for the residual form
         const double n = (double)h->n;
@@ -937,7 +938,7 @@ void csr(mgr_handle *h, int mode, const DCsr &A, const T *vals, const T *x, cons
 template <typename T>
 void sweep(mgr_handle *h, const AmgHier &H, int k, const DCsr &A, const T *vals, const T *x, const T *r,
            const T *d, T *y) {
-    const bool timed = h->timing && &H == &h->cg && k == 0;
+    const bool timed = h->timing && &H == &h->cg && k == 0 && A.nrows > 0;
     csr<T>(h, 3, A, vals, x, r, d, y, timed ? timer_kernel(h, h->tm[2]) : KEvents{});
     if (timed) {
         h->tm[2].bytes += csr_bytes(A, 3, sizeof(T));
