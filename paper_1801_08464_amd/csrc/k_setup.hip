@@ -920,15 +920,44 @@ __global__ void __launch_bounds__(256) k_interp_fill_grp(
     double *num = s_num[w], *aij = s_aij[w];
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     const int a = rp[i], b = rp[i + 1];
+    // Row i's entries, G at a time: from registers when the row fits in
+    // kInterpRowChunks chunks (loaded once for the three passes below), else
+    // from memory in each pass.  Each pass's body sees one chunk: the entry's
+    // presence, column, value, strength flag and the column's C/F mark.
+    const bool rowreg = b - a <= G * kInterpRowChunks;  // the same for the whole group
+    int rj[kInterpRowChunks], rcf[kInterpRowChunks];
+    double rv[kInterpRowChunks];
+    bool rs[kInterpRowChunks];
+    if (rowreg) {
+#pragma unroll
+        for (int u = 0; u < kInterpRowChunks; ++u) {
+            const int p = a + u * G + lane;
+            const bool ok = p < b;
+            rj[u] = ok ? ci[p] : -1;
+            rv[u] = ok ? v[p] : 0.0;
+            rs[u] = ok && sflag[p];
+            rcf[u] = ok ? cf[rj[u]] : 0;
+        }
+    }
+    auto each_chunk = [&](auto &&body) {
+        if (rowreg) {
+#pragma unroll
+            for (int u = 0; u < kInterpRowChunks; ++u)
+                if (a + u * G < b) body(a + u * G + lane < b, rj[u], rv[u], rs[u], rcf[u]);
+        } else {
+            for (int c0 = a; c0 < b; c0 += G) {
+                const int p = c0 + lane;
+                const bool ok = p < b;
+                const int j = ok ? ci[p] : -1;
+                body(ok, j, ok ? v[p] : 0.0, ok && sflag[p], ok ? cf[j] : 0);
+            }
+        }
+    };
     // the strong C neighbours (ascending) and the diagonal
     int nc = 0;
     double aii = 0.0;
-    for (int c0 = a; c0 < b; c0 += G) {
-        const int p = c0 + lane;
-        const bool ok = p < b;
-        const int j = ok ? ci[p] : -1;
-        const double vv = ok ? v[p] : 0.0;
-        const bool sc = ok && sflag[p] && cf[j] == 1;
+    each_chunk([&](bool ok, int j, double vv, bool sf, int cfj) {
+        const bool sc = ok && sf && cfj == 1;
         const unsigned long long m = grp.ballot(sc);
         if (sc) {
             const int pos = nc + __popcll(m & below);
@@ -940,23 +969,17 @@ __global__ void __launch_bounds__(256) k_interp_fill_grp(
         nc += __popcll(m);
         const unsigned long long md = grp.ballot(ok && j == i);
         if (md) aii = grp.shfl(vv, __builtin_ctzll(md));
-    }
+    });
     wave_sync();
     // atil = a_ii + the weak entries, ascending
     double atil = aii;
-    for (int c0 = a; c0 < b; c0 += G) {
-        const int p = c0 + lane;
-        const bool ok = p < b;
-        const bool weak = ok && ci[p] != i && !sflag[p];
-        atil = grp.ordered_add(atil, grp.ballot(weak), ok ? v[p] : 0.0);
-    }
+    each_chunk([&](bool ok, int j, double vv, bool sf, int) {
+        const bool weak = ok && j != i && !sf;
+        atil = grp.ordered_add(atil, grp.ballot(weak), vv);
+    });
     // the strong F neighbours k, ascending
-    for (int c0 = a; c0 < b; c0 += G) {
-        const int p = c0 + lane;
-        const bool ok = p < b;
-        const int j = ok ? ci[p] : -1;
-        const double vv = ok ? v[p] : 0.0;
-        unsigned long long mk = grp.ballot(ok && j != i && sflag[p] && cf[j] == -1);
+    each_chunk([&](bool ok, int j, double vv, bool sf, int cfj) {
+        unsigned long long mk = grp.ballot(ok && j != i && sf && cfj == -1);
         while (mk) {
             const int l = __builtin_ctzll(mk);
             mk &= mk - 1;
@@ -1040,7 +1063,7 @@ __global__ void __launch_bounds__(256) k_interp_fill_grp(
             }
             wave_sync();
         }
-    }
+    });
     wave_sync();
     for (int t = lane; t < nc; t += G) {
         const double sum = aij[t] + num[t];
