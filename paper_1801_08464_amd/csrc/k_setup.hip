@@ -472,26 +472,6 @@ __global__ void k_transpose_fill(int64_t nrows, const int32_t *rp, const int32_t
     }
 }
 
-// the slots of a row were taken in arbitrary order; source rows are unique,
-// so sorting by source row gives the one stable order
-__global__ void k_transpose_sort(int64_t ncols, const int32_t *Trp, int32_t *Tci, double *Tv) {
-    int64_t j = gtid();
-    if (j >= ncols) return;
-    int a = Trp[j], b = Trp[j + 1];
-    for (int p = a + 1; p < b; ++p) {
-        int key = Tci[p];
-        double val = Tv ? Tv[p] : 0.0;
-        int q = p - 1;
-        while (q >= a && Tci[q] > key) {
-            Tci[q + 1] = Tci[q];
-            if (Tv) Tv[q + 1] = Tv[q];
-            q--;
-        }
-        Tci[q + 1] = key;
-        if (Tv) Tv[q + 1] = val;
-    }
-}
-
 // ---------------- classical strength of connection ----------------
 // j in S_i iff j != i, m_i > 0 and -s_i a_ij >= theta m_i, s_i = sign of a_ii (+ for 0)
 // G lanes per row: the diagonal by ballot, m_i by a group max (exact in any
@@ -775,6 +755,57 @@ struct InterpGroup {
         return acc;
     }
 };
+
+// The sort of a transpose's rows (the slots were taken in arbitrary order;
+// source rows are unique, so sorting by source row gives the one stable order)
+// with a group of kSortLanes lanes per row: rows of up to kSortMaxLen entries
+// are staged in LDS and each entry is written at its rank (the number of
+// smaller keys in the row); a longer row is sorted by insertion in the group's
+// first lane.
+constexpr int kSortLanes = 8;
+constexpr int kSortMaxLen = 64;
+__global__ void __launch_bounds__(256) k_transpose_sort_grp(int64_t ncols, const int32_t *__restrict__ Trp,
+                                                            int32_t *__restrict__ Tci, double *__restrict__ Tv) {
+    constexpr int RPB = 256 / kSortLanes;
+    __shared__ int sk[RPB][kSortMaxLen];
+    __shared__ double sv[RPB][kSortMaxLen];
+    const int lane = threadIdx.x & (kSortLanes - 1), w = threadIdx.x / kSortLanes;
+    const int64_t j = (int64_t)blockIdx.x * RPB + w;
+    if (j >= ncols) return;  // uniform per group
+    const int a = Trp[j], len = Trp[j + 1] - a;
+    if (len <= 1) return;
+    if (len > kSortMaxLen) {
+        if (lane == 0) {
+            for (int p = a + 1; p < a + len; ++p) {
+                const int key = Tci[p];
+                const double val = Tv ? Tv[p] : 0.0;
+                int q = p - 1;
+                while (q >= a && Tci[q] > key) {
+                    Tci[q + 1] = Tci[q];
+                    if (Tv) Tv[q + 1] = Tv[q];
+                    q--;
+                }
+                Tci[q + 1] = key;
+                if (Tv) Tv[q + 1] = val;
+            }
+        }
+        return;
+    }
+    int *k = sk[w];
+    double *kv = sv[w];
+    for (int e = lane; e < len; e += kSortLanes) {
+        k[e] = Tci[a + e];
+        if (Tv) kv[e] = Tv[a + e];
+    }
+    wave_sync();  // the group lies in one wavefront
+    for (int e = lane; e < len; e += kSortLanes) {
+        const int key = k[e];
+        int r = 0;
+        for (int f = 0; f < len; ++f) r += k[f] < key;
+        Tci[a + r] = key;
+        if (Tv) Tv[a + r] = kv[e];
+    }
+}
 
 // ---------------- row selections: P = [W_p; I_C], A_FF, the F columns ----------------
 // A group of G lanes takes one row and its entries G at a time (coalesced
@@ -1313,7 +1344,7 @@ void launch_transpose_fill(int64_t nrows, const int32_t *rp, const int32_t *ci, 
     if (nrows > 0) k_transpose_fill<<<nblocks(nrows, BT), BT, 0, s>>>(nrows, rp, ci, v, next, Tci, Tv);
 }
 void launch_transpose_sort(int64_t ncols, const int32_t *Trp, int32_t *Tci, double *Tv, hipStream_t s) {
-    if (ncols > 0) k_transpose_sort<<<nblocks(ncols, BT), BT, 0, s>>>(ncols, Trp, Tci, Tv);
+    if (ncols > 0) k_transpose_sort_grp<<<nblocks(ncols, 256 / kSortLanes), 256, 0, s>>>(ncols, Trp, Tci, Tv);
 }
 template <int G>
 static void strength_g(int pass, int64_t n, const int32_t *rp, const int32_t *ci, const double *v, double theta,
